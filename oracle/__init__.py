@@ -1,0 +1,272 @@
+"""FP64 CPU oracle (ctypes front end of ``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg.  It never imports the HIP package and the
+HIP package never imports it.
+
+Expressions are written with the small builder below in the paper's notation
+(``%`` is the Schur product, Sec. 4; capital letters are matrices, lower case
+scalars) and evaluated node by node with one FP64 temporary per node.  The
+builder knows nothing of the HIP path's expression templates.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+
+DTYPE = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3, "u32": 4}
+OP = {"leaf": 0, "const": 1, "add": 2, "sub": 3, "mul": 4, "div": 5, "neg": 6,
+      "abs": 7, "exp": 8, "sqrt": 9, "xor": 10}
+REDUCE = {None: 0, "accu": 1, "colsum": 2, "rowsum": 3, "norm": 4}
+
+U32 = 2.0 ** -24   # unit roundoff, FP32 compute (f32, bf16, f16 storage)
+U64 = 2.0 ** -53   # unit roundoff, FP64 compute
+TOL = {"f32": 1e-6, "bf16": 1e-6, "f16": 1e-6, "f64": 1e-13}
+U_HALF = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+HALF_SUBNORMAL_HALF_SPACING = {"bf16": 2.0 ** -134, "f16": 2.0 ** -25}
+
+
+def build(force: bool = False) -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        L.or_eval.restype = ctypes.c_int
+        L.or_eval.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
+                              ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                              ctypes.c_double, ctypes.c_double, P, P]
+        L.or_eval_u32.restype = ctypes.c_int
+        L.or_eval_u32.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P,
+                                  ctypes.c_int64, P, P]
+        L.or_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+# --------------------------------------------------------------------------
+# Expression builder: a tree of nodes, flattened children-first.
+
+
+class E:
+    """A node of an expression tree."""
+
+    __slots__ = ("op", "kids", "leaf", "cst")
+
+    def __init__(self, op, kids=(), leaf=-1, cst=0.0):
+        self.op, self.kids, self.leaf, self.cst = op, tuple(kids), leaf, cst
+
+    @staticmethod
+    def wrap(v):
+        return v if isinstance(v, E) else const(v)
+
+    def __add__(self, o): return E("add", (self, E.wrap(o)))
+    def __radd__(self, o): return E("add", (E.wrap(o), self))
+    def __sub__(self, o): return E("sub", (self, E.wrap(o)))
+    def __rsub__(self, o): return E("sub", (E.wrap(o), self))
+    def __mod__(self, o): return E("mul", (self, E.wrap(o)))     # Schur product
+    def __mul__(self, o):                                         # scalar * matrix only
+        assert not isinstance(o, E), "matrix product is not an element-wise operation"
+        return E("mul", (self, const(o)))
+    def __rmul__(self, o):
+        assert not isinstance(o, E)
+        return E("mul", (const(o), self))
+    def __truediv__(self, o): return E("div", (self, E.wrap(o)))
+    def __rtruediv__(self, o): return E("div", (E.wrap(o), self))
+    def __neg__(self): return E("neg", (self,))
+    def __xor__(self, o): return E("xor", (self, E.wrap(o)))
+
+    def nodes(self):
+        """Post-order list of distinct nodes (root last)."""
+        order, seen = [], {}
+
+        def visit(e):
+            if id(e) in seen:
+                return
+            for k in e.kids:
+                visit(k)
+            seen[id(e)] = len(order)
+            order.append(e)
+
+        visit(self)
+        return order, seen
+
+    def arrays(self):
+        order, seen = self.nodes()
+        n = len(order)
+        op = np.array([OP[e.op] for e in order], dtype=np.int32)
+        a = np.array([seen[id(e.kids[0])] if len(e.kids) > 0 else -1 for e in order], np.int32)
+        b = np.array([seen[id(e.kids[1])] if len(e.kids) > 1 else -1 for e in order], np.int32)
+        leaf = np.array([e.leaf for e in order], dtype=np.int32)
+        cst = np.array([e.cst for e in order], dtype=np.float64)
+        assert n == op.size
+        return op, a, b, leaf, cst
+
+    def n_inputs(self):
+        order, _ = self.nodes()
+        return 1 + max([e.leaf for e in order] + [-1])
+
+
+def leaf(i: int) -> E:
+    return E("leaf", leaf=i)
+
+
+def const(c: float) -> E:
+    return E("const", cst=float(c))
+
+
+def exp(e): return E("exp", (e,))
+def abs_(e): return E("abs", (e,))
+def sqrt(e): return E("sqrt", (e,))
+
+
+X, Y, W = leaf(0), leaf(1), leaf(2)
+
+# The expressions of the workloads, in the paper's API notation.
+EXPRS = {
+    "c1_z": X % Y + 2 * W,                          # Z = X % Y + 2*W
+    "xy": X % Y,                                    # accu(X % Y), dot(X, Y), sum(X % Y, 0)
+    "c2_z": (X + Y) % exp(-abs_(W)) / (1 + X % X),  # C++ precedence: ((X+Y)%exp(-|W|)) / (1+X%X)
+    "diff": X - Y,                                  # norm_fro(X - Y)
+    "u32_z": (X ^ Y) + 3 * W,                       # (X ^ Y) + 3*W mod 2^32
+}
+
+
+def axy_expw(a: float) -> E:
+    """Z = a*X % Y + exp(-W) for a run-time scalar a (the scalar is held in
+    the compute type by the caller, so pass it already rounded)."""
+    return a * X % Y + exp(-W)
+
+
+# --------------------------------------------------------------------------
+
+
+def _ptrs(inputs):
+    arr = (ctypes.c_void_p * max(1, len(inputs)))()
+    for i, x in enumerate(inputs):
+        arr[i] = x.ctypes.data
+    return arr
+
+
+def compute_unit(dtype: str) -> float:
+    return U64 if dtype == "f64" else U32
+
+
+def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
+             fexp: float = 2.0):
+    """Evaluate `expr` over stored inputs (numpy arrays of the storage dtype,
+    bf16 as uint16 bit patterns).  shape=(n_rows, n_cols), column-major;
+    default (n, 1).  Returns (value, mu): arrays of FP64 values and running
+    error bounds in units of u_c (default: the compute type's roundoff)."""
+    inputs = [np.ascontiguousarray(x).reshape(-1, order="F") if x.ndim > 1 else
+              np.ascontiguousarray(x) for x in inputs]
+    n = inputs[0].size if inputs else 0
+    if shape is None:
+        shape = (n, 1)
+    rows, cols = shape
+    assert all(x.size == rows * cols for x in inputs)
+    assert expr.n_inputs() <= len(inputs)
+    if u_c is None:
+        u_c = compute_unit(dtype)
+    op, a, b, lf, cst = expr.arrays()
+    red = REDUCE[reduce]
+    nout = {0: rows * cols, 1: 1, 2: cols, 3: rows, 4: 1}[red]
+    out = np.empty(max(nout, 1), np.float64)
+    mu = np.empty(max(nout, 1), np.float64)
+    rc = lib().or_eval(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
+                       lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
+                       DTYPE[dtype], rows, cols, red, u_c, fexp, out.ctypes.data,
+                       mu.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle evaluation failed (%d)" % rc)
+    return out[:nout], mu[:nout]
+
+
+def evaluate_u32(expr: E, inputs):
+    """Integer tree over u32 inputs; returns (values u32[n], full u64 sum)."""
+    inputs = [np.ascontiguousarray(x, dtype=np.uint32) for x in inputs]
+    n = inputs[0].size
+    op, a, b, lf, cst = expr.arrays()
+    out = np.empty(max(n, 1), np.uint32)
+    tot = np.zeros(1, np.uint64)
+    rc = lib().or_eval_u32(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
+                           lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
+                           n, out.ctypes.data, tot.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle evaluation failed (%d)" % rc)
+    return out[:n], int(tot[0])
+
+
+# --------------------------------------------------------------------------
+# The acceptance rule for floating-point results.
+
+
+def allowed_error(value, mu, dtype: str, out_dtype: str | None = None):
+    """Largest admissible |result - value| for a result computed in the
+    compute type of `dtype`:  max(tol*|value|, 4*u_c*mu).  If the result is
+    stored in a half format (`out_dtype` bf16/f16), the final rounding adds
+    u_half*(|value| + that) plus half the subnormal spacing."""
+    value = np.asarray(value, np.float64)
+    mu = np.asarray(mu, np.float64)
+    u_c = compute_unit(dtype)
+    base = np.maximum(TOL[dtype] * np.abs(value), 4.0 * u_c * mu)
+    if out_dtype in U_HALF:
+        base = 4.0 * u_c * mu + U_HALF[out_dtype] * (np.abs(value) + 4.0 * u_c * mu) \
+            + HALF_SUBNORMAL_HALF_SPACING[out_dtype]
+    return base
+
+
+def check(result, value, mu, dtype: str, out_dtype: str | None = None):
+    """Element-wise pass mask plus a small report.  NaN must match NaN and
+    infinities must match in sign."""
+    r = np.asarray(result, np.float64)
+    v = np.asarray(value, np.float64)
+    lim = allowed_error(v, mu, dtype, out_dtype)
+    with np.errstate(invalid="ignore", over="ignore"):
+        err = np.abs(r - v)
+        ok = err <= lim
+    nan = np.isnan(v)
+    ok = np.where(nan, np.isnan(r), ok)
+    inf = np.isinf(v)
+    ok = np.where(inf, r == v, ok)
+    rel_branch = np.asarray(TOL[dtype] * np.abs(v) >= 4.0 * compute_unit(dtype) * np.asarray(mu))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel = np.where(v != 0, err / np.abs(v), err)
+    report = {
+        "n": int(r.size),
+        "fail": int(r.size - np.count_nonzero(ok)),
+        "max_rel": float(np.nanmax(rel)) if r.size else 0.0,
+        "max_err_over_allowed": float(np.nanmax(np.where(lim > 0, err / lim, err)))
+        if r.size else 0.0,
+        "cancellation_dominated": int(np.count_nonzero(~rel_branch)),
+    }
+    return ok, report
+
+
+def ceil_log2(n: int) -> int:
+    return 0 if n <= 1 else math.ceil(math.log2(n))
