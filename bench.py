@@ -1,0 +1,285 @@
+"""Benchmark of the fused expression path on one MI355X.
+
+A step is one pass of the fused hot path over the matrix workload: FP32
+8192 x 8192 column-major X, Y, W ~ U[-1,1] (seeded), computing
+    Z = (X + Y) % exp(-abs(W)) / (1 + X % X)      (element-wise)
+    sum(Z, 0)                                       (column sums, fused)
+    norm_fro(X - Y)                                 (Frobenius norm, fused)
+Protocol: W untimed warm-up steps, then K timed steps (the paper's protocol is
+2 warm-ups and the mean of 50 runs, Sec. 4).  `value` is algorithmic bytes
+(distinct inputs read once + outputs written once) over the wall time of the
+timed region, in GB/s.  Alongside: per-kernel HIP-event times, the same
+results through the unfused one-kernel-per-operator baseline, the same
+workload with BF16 storage, the copy ceiling, and the FP64 CPU oracle timed
+on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, vendor figure
+ROWS = COLS = 8192
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(dtype, n, seed=2):
+    import numpy as np
+    import torch
+
+    import synth
+    out = []
+    for t in range(3):
+        h = synth.fill(seed, t, n, dtype)
+        tt = torch.from_numpy(h)
+        if dtype == "bf16":
+            tt = tt.view(torch.int16).view(torch.bfloat16)
+        out.append(tt.to("cuda"))
+        del h
+    return out
+
+
+class Workload:
+    """The three fused results (or their unfused evaluation) on one dtype."""
+
+    def __init__(self, fx, torch, dtype, rows, cols):
+        self.fx, self.torch = fx, torch
+        self.dtype, self.shape = dtype, (rows, cols)
+        n = rows * cols
+        self.X, self.Y, self.W = make_inputs(dtype, n)
+        tdt = self.X.dtype
+        acc = torch.float32
+        self.Z = torch.empty(n, dtype=tdt, device="cuda")
+        self.cs = torch.empty(cols, dtype=acc, device="cuda")
+        self.nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dt = fx.dtype_code(self.X)
+        self.ws_c = fx.workspace(fx.R_COLSUM, dt, self.shape)
+        self.ws_n = fx.workspace(fx.R_NORM, dt, self.shape)
+        esz = self.X.element_size()
+        # algorithmic bytes: distinct inputs read once, outputs written once
+        self.bytes = {"z": 4 * n * esz, "colsum": 3 * n * esz + cols * 4, "norm": 2 * n * esz + 8}
+        self.tmp = None
+
+    def fused(self, which, stream):
+        fx = self.fx
+        if which == "z":
+            fx.fx_c2_z(self.X, self.Y, self.W, self.Z, self.shape, stream=stream)
+        elif which == "colsum":
+            fx.fx_c2_colsum(self.X, self.Y, self.W, self.cs, self.shape, self.ws_c, stream=stream)
+        else:
+            fx.fx_norm_fro_diff(self.X, self.Y, self.nrm, self.shape, self.ws_n, stream=stream)
+
+    def unfused(self, which, stream):
+        fx, torch = self.fx, self.torch
+        if self.tmp is None:
+            nb = fx.fx_unfused_tmp_bytes("c2_colsum", fx.dtype_code(self.X), self.shape)
+            self.tmp = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        ins = [self.X, self.Y, self.W]
+        if which == "z":
+            fx.fx_unfused("c2_z", ins, self.Z, self.shape, self.tmp, stream=stream)
+        elif which == "colsum":
+            fx.fx_unfused("c2_colsum", ins, self.cs, self.shape, self.tmp, self.ws_c, stream=stream)
+        else:
+            fx.fx_unfused("norm_diff", ins[:2], self.nrm, self.shape, self.tmp, self.ws_n,
+                          stream=stream)
+
+
+RESULTS = ("z", "colsum", "norm")
+
+
+def time_steps(torch, run, steps, warmup, stream):
+    """W warm-up steps, then K timed steps; returns (wall seconds, per-result
+    mean kernel ms from HIP events recorded on the launch stream)."""
+    for _ in range(warmup):
+        for r in RESULTS:
+            run(r, stream)
+    torch.cuda.synchronize()
+    ev = {r: [] for r in RESULTS}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in RESULTS:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run(r, stream)
+            b.record(stream)
+            ev[r].append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = {r: sum(a.elapsed_time(b) for a, b in ev[r]) / steps for r in RESULTS}
+    return wall, ms
+
+
+def copy_ceiling(fx, torch, stream, nbytes=1 << 31, reps=20):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        fx.fx_bw_copy(src, dst, nbytes, stream=stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fx.fx_bw_copy(src, dst, nbytes, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
+                  for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp")]
+
+
+def measured_traffic(kernel_tag="k_ew[c2,f32"):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if there is none or the
+    kernel sources have changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+    m = re.search(r"Kernel source hash[^:]*: ([0-9a-f]{16})", text)
+    if not m or m.group(1) != h:
+        return None
+    for line in text.splitlines():
+        if line.startswith("| fx::" + kernel_tag):
+            cells = [c.strip() for c in line.strip("|").split("|")]
+            return int(round((float(cells[5]) + float(cells[6])) * 2 ** 20))
+    return None
+
+
+def cpu_baseline(cols_sample=COLS, min_seconds=10.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
+    same three results over the first `cols_sample` columns, repeated until
+    at least `min_seconds` of CPU work has been timed."""
+    import oracle
+    import synth
+    n = ROWS * cols_sample
+    host = [synth.fill(2, t, n, "f32") for t in range(3)]
+    shape = (ROWS, cols_sample)
+    e = oracle.EXPRS["c2_z"]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.evaluate(e, host, "f32", shape=shape)
+        oracle.evaluate(e, host, "f32", shape=shape, reduce="colsum")
+        oracle.evaluate(oracle.EXPRS["diff"], host[:2], "f32", shape=shape, reduce="norm")
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    nbytes = reps * (16 * n + 12 * n + 8 * n)
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "C2 FP32 Z, sum(Z,0), norm_fro(X-Y) over 8192 x %d columns, %d repetitions "
+                      "in %.1f s (FP64, explicit temporaries)" % (cols_sample, reps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the fused FP32 steps")
+    ap.add_argument("--profile", action="store_true",
+                    help="fused FP32 steps plus one 1 GiB copy (the known-size kernel that "
+                         "scales hardware byte counters); no CPU baseline")
+    a = ap.parse_args()
+    if a.profile:
+        a.no_extra = a.no_cpu = True
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this path has no multi-GPU form "
+              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2604_22242_amd as fx
+    fx.lib()
+    stream = torch.cuda.current_stream()
+    log("bench: fused FP32 %dx%d, %d warm-up + %d timed steps" % (ROWS, COLS, a.warmup, a.steps))
+    wl = Workload(fx, torch, "f32", ROWS, COLS)
+    wall, ms = time_steps(torch, wl.fused, a.steps, a.warmup, stream)
+    step_bytes = sum(wl.bytes.values())
+    value = step_bytes * a.steps / wall / 1e9
+    per = {r: {"ms": round(ms[r], 5), "GB/s": round(wl.bytes[r] / (ms[r] * 1e-3) / 1e9, 1)}
+           for r in RESULTS}
+    detail = {"fp32_fused": per}
+    dominant = max(RESULTS, key=lambda r: ms[r])
+    achieved = wl.bytes[dominant] / (ms[dominant] * 1e-3) / 1e9
+
+    if not a.no_extra:
+        log("bench: unfused FP32 baseline")
+        _, ums = time_steps(torch, wl.unfused, a.steps, a.warmup, stream)
+        detail["fp32_unfused_ms"] = {r: round(ums[r], 5) for r in RESULTS}
+        detail["speedup_vs_unfused"] = {r: round(ums[r] / ms[r], 3) for r in RESULTS}
+        del wl
+        torch.cuda.empty_cache()
+        log("bench: fused BF16 storage")
+        wb = Workload(fx, torch, "bf16", ROWS, COLS)
+        _, bms = time_steps(torch, wb.fused, a.steps, a.warmup, stream)
+        _, bums = time_steps(torch, wb.unfused, a.steps, a.warmup, stream)
+        detail["bf16_fused"] = {r: {"ms": round(bms[r], 5),
+                                    "GB/s": round(wb.bytes[r] / (bms[r] * 1e-3) / 1e9, 1)}
+                                for r in RESULTS}
+        detail["bf16_speedup_vs_unfused"] = {r: round(bums[r] / bms[r], 3) for r in RESULTS}
+        detail["bf16_speedup_vs_fp32_storage"] = {r: round(ms[r] / bms[r], 3) for r in RESULTS}
+        del wb
+        torch.cuda.empty_cache()
+        log("bench: copy ceiling")
+        detail["copy_ceiling_GB/s"] = round(copy_ceiling(fx, torch, stream), 1)
+
+    if a.profile:
+        log("bench: 1 GiB reference copy")
+        copy_ceiling(fx, torch, stream, nbytes=1 << 30, reps=1)
+
+    cpu = None
+    if not a.no_cpu:
+        log("bench: CPU oracle baseline")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "fused-expr HBM GB/s (% of peak) + speedup vs unfused, FP32 & BF16 storage",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 2),
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (SplitMix64 seed 2, U[-1,1])",
+        "config": {"workload": "C2 matrix expressions: Z=(X+Y)%exp(-abs(W))/(1+X%X), sum(Z,0), "
+                               "norm_fro(X-Y); FP32 8192x8192 column-major",
+                   "rows": ROWS, "cols": COLS, "bytes_per_step": step_bytes},
+        "roofline": {"bound": "hbm", "kernel": "c2_" + dominant,
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic() if dominant == "z" else None,
+                     "algorithmic_bytes": wl.bytes[dominant]},
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * fx.h - C ABI of the fused element-wise expression library (libfx.so) for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What it implements: the compile-time expression fusion of Curtin, Edel and
+ * Sanderson, "Fast GPU Linear Algebra via Compile Time Expression Fusion".
+ * An expression such as Z = X % Y + 2*W (% = Schur product, Sec. 4) is
+ * captured as a C++ type (Sec. 3, the X.t()+3 example), and one kernel reads
+ * every input once and writes the output once, with no temporaries (Sec. 3,
+ * skeleton kernels; Sec. 5, "single pass").  The fused entry points below
+ * are instances of that front end for fixed expressions; fx_tape_* (when
+ * present) evaluates trees only known at run time.
+ *
+ * Conventions shared by every call:
+ *   - Matrices are dense, column-major, leading dimension n_rows: element
+ *     (r, c) lives at linear index r + c*n_rows (Sec. 3, element access of a
+ *     plain matrix).  Vectors are n x 1.
+ *   - All data pointers are DEVICE pointers owned by the caller.  The
+ *     library never frees or retains them after the enqueued work completes.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it and returns at once; results are ready when the
+ *     stream is synchronised (Sec. 2: asynchronous dispatch, synchronisation
+ *     on demand, cf. coot_synchronise()).
+ *   - Scalar reduction results are written to device memory as FP64 so the
+ *     call stays asynchronous; reading them synchronises.
+ *   - `cfg` may be NULL; any zero field is chosen by the library.
+ *   - Every call returns an fx_status.  Arguments are validated on the host
+ *     before anything is enqueued; on error nothing is enqueued and
+ *     fx_last_error() (thread-local) describes the problem.  Faults inside a
+ *     kernel surface at the caller's next synchronisation.
+ *   - n = 0 (or an empty shape) is a valid no-op; a scalar reduction of
+ *     nothing writes 0.
+ *   - Pointers need only the alignment of their element type; 16-byte
+ *     vector loads are used when every pointer of a call is 16-byte aligned,
+ *     element-wise loads otherwise.
+ *   - An element-wise output may be exactly one of the inputs (in place);
+ *     partial overlap is not allowed.
+ *
+ * Workspaces: reductions that combine results across blocks take a caller
+ * allocated device workspace of fx_workspace_bytes() bytes, which must be
+ * zero-filled once before its first use; the library leaves it zeroed again
+ * after every call (its counters reset themselves).  One workspace must not
+ * be used by two calls that may run concurrently.
+ */
+#ifndef FX_H
+#define FX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage types.  BF16/F16 are computed in FP32 (low-precision storage,
+ * Sec. 5 future work); F64 in FP64; U32 in u32 arithmetic mod 2^32. */
+typedef enum { FX_F32 = 0, FX_F64 = 1, FX_BF16 = 2, FX_F16 = 3, FX_U32 = 4 } fx_dtype;
+
+typedef enum {
+  FX_OK = 0,
+  FX_E_ARG = 1,         /* NULL pointer, negative size, bad enum value */
+  FX_E_SHAPE = 2,       /* incompatible dimensions */
+  FX_E_DTYPE = 3,       /* dtype not supported by this call */
+  FX_E_WORKSPACE = 4,   /* workspace missing or too small */
+  FX_E_HIP = 5,         /* HIP runtime error (text in fx_last_error) */
+  FX_E_UNSUPPORTED = 6, /* launch configuration outside the compiled set */
+  FX_E_CONFIG = 7       /* malformed launch configuration */
+} fx_status;
+
+/* Launch configuration; 0 in a field means "library default".
+ *   block:     threads per block, a multiple of 64 in [64, 512]
+ *   ept:       independent vector loads per input per thread, 1/2/4/8
+ *   vec_bytes: bytes per vector load: 4, 8 or 16 (at least one element)
+ *   split:     element-wise and full reductions: number of blocks (grid);
+ *              column sums: blocks per column; row sums: column chunks. */
+typedef struct { int32_t block, ept, vec_bytes, split; } fx_launch;
+
+typedef struct { int64_t n_rows, n_cols; } fx_shape;
+
+/* Reduction kinds (Sec. 3 names accu(); the others follow Armadillo, whose
+ * API the library mirrors, Sec. 2). */
+typedef enum {
+  FX_R_ACCU = 1,   /* sum of all elements -> double             */
+  FX_R_COLSUM = 2, /* sum(E, 0): 1 x n_cols, accumulator dtype  */
+  FX_R_ROWSUM = 3, /* sum(E, 1): n_rows x 1, accumulator dtype  */
+  FX_R_NORM = 4,   /* Frobenius norm sqrt(sum E^2) -> double    */
+  FX_R_DOT = 5     /* sum A_i * B_i -> double                   */
+} fx_reduce_kind;
+
+/* Element-wise operators of the unfused baseline (one kernel each). */
+typedef enum {
+  FX_OP_NEG = 1, FX_OP_ABS = 2, FX_OP_EXP = 3, FX_OP_SQRT = 4,      /* unary  */
+  FX_OP_ADD = 10, FX_OP_SUB = 11, FX_OP_SCHUR = 12, FX_OP_DIV = 13, /* binary */
+  FX_OP_XOR = 14,                                                   /* u32    */
+  FX_OP_SADD = 20,  /* k + A */
+  FX_OP_SMUL = 21,  /* k * A */
+  FX_OP_SDIV = 22,  /* A / k */
+  FX_OP_SRDIV = 23, /* k / A */
+  FX_OP_SSUB = 24,  /* A - k */
+  FX_OP_SRSUB = 25  /* k - A */
+} fx_op;
+
+/* The workload expressions, for fx_unfused() and fx_workspace_bytes(). */
+typedef enum {
+  FX_EXPR_C1_Z = 1,       /* Z = X % Y + 2*W  (U32: Z = (X ^ Y) + 3*W)  */
+  FX_EXPR_ACCU_XY = 2,    /* accu(X % Y)                                */
+  FX_EXPR_C2_Z = 3,       /* Z = (X + Y) % exp(-abs(W)) / (1 + X % X)   */
+  FX_EXPR_C2_COLSUM = 4,  /* sum(C2 expression, 0)                      */
+  FX_EXPR_C2_ROWSUM = 5,  /* sum(C2 expression, 1)                      */
+  FX_EXPR_NORM_DIFF = 6,  /* norm_fro(X - Y)                            */
+  FX_EXPR_COLSUM_XY = 7,  /* sum(X % Y, 0)                              */
+  FX_EXPR_AXY_EXPW = 8    /* Z = a*X % Y + exp(-W)                      */
+} fx_expr_id;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Version string; never NULL. */
+const char* fx_version(void);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* fx_last_error(void);
+
+/* Blocks until all work enqueued on `stream` has finished (the library's
+ * coot_synchronise(), Sec. 2).  Returns FX_E_HIP if that work faulted. */
+int fx_synchronize(void* stream);
+
+/* Workspace bytes needed by reduction `kind` (FX_R_*) over an expression of
+ * storage dtype `dt` and shape `shape` under launch configuration `cfg`
+ * (NULL = defaults).  Returns 0 on bad arguments. */
+size_t fx_workspace_bytes(int kind, fx_dtype dt, fx_shape shape, const fx_launch* cfg);
+
+/* The configuration the library would use for reduction kind `kind`
+ * (0 = element-wise) with these arguments, written to *out.  Returns
+ * FX_E_CONFIG / FX_E_ARG on invalid input. */
+int fx_resolve_launch(int kind, fx_dtype dt, fx_shape shape, const fx_launch* cfg,
+                      fx_launch* out);
+
+/* ---- fused entry points (compile-time expression templates) --------------
+ * Each is one kernel launch that reads each distinct input once and writes
+ * its output once (Sec. 3, skeleton kernels; Sec. 5). */
+
+/* Z[i] = X[i]*Y[i] + 2*W[i] for i < n (FP dtypes);
+ * Z[i] = (X[i] ^ Y[i]) + 3*W[i] mod 2^32 (FX_U32). */
+int fx_c1_z(fx_dtype dt, const void* X, const void* Y, const void* W, void* Z,
+            int64_t n, const fx_launch* cfg, void* stream);
+
+/* Z = a*X % Y + exp(-W), with a rounded to the compute type. FP dtypes. */
+int fx_axy_expw(fx_dtype dt, double a, const void* X, const void* Y, const void* W,
+                void* Z, int64_t n, const fx_launch* cfg, void* stream);
+
+/* *d_out = accu(X % Y) = sum_i X[i]*Y[i], as FP64 (FP dtypes) or, for
+ * FX_U32, the full u64 sum stored in d_out's 8 bytes.  Per-thread sums are
+ * compensated (Neumaier) in the compute type and combined in FP64 in a fixed
+ * order by the last block to finish.  ws: fx_workspace_bytes(FX_R_ACCU). */
+int fx_accu_xy(fx_dtype dt, const void* X, const void* Y, int64_t n, void* d_out,
+               void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream);
+
+/* dot(X, Y): the same value as fx_accu_xy (identical kernel and order). */
+int fx_dot(fx_dtype dt, const void* X, const void* Y, int64_t n, void* d_out,
+           void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream);
+
+/* Z = (X + Y) % exp(-abs(W)) / (1 + X % X), element-wise over `shape`.
+ * FP dtypes. */
+int fx_c2_z(fx_dtype dt, const void* X, const void* Y, const void* W, void* Z,
+            fx_shape shape, const fx_launch* cfg, void* stream);
+
+/* out[c] = sum_r E(r, c) for the C2 expression E: 1 x n_cols, written in the
+ * accumulator dtype (float for F32/BF16/F16, double for F64).
+ * ws: fx_workspace_bytes(FX_R_COLSUM). */
+int fx_c2_colsum(fx_dtype dt, const void* X, const void* Y, const void* W, void* out,
+                 fx_shape shape, void* ws, size_t ws_bytes, const fx_launch* cfg,
+                 void* stream);
+
+/* out[r] = sum_c E(r, c) for the C2 expression E: n_rows x 1, accumulator
+ * dtype.  ws: fx_workspace_bytes(FX_R_ROWSUM). */
+int fx_c2_rowsum(fx_dtype dt, const void* X, const void* Y, const void* W, void* out,
+                 fx_shape shape, void* ws, size_t ws_bytes, const fx_launch* cfg,
+                 void* stream);
+
+/* *d_out = norm_fro(X - Y) = sqrt(sum (X - Y)^2) as FP64.
+ * ws: fx_workspace_bytes(FX_R_NORM). */
+int fx_norm_fro_diff(fx_dtype dt, const void* X, const void* Y, fx_shape shape,
+                     double* d_out, void* ws, size_t ws_bytes, const fx_launch* cfg,
+                     void* stream);
+
+/* out[c] = sum_r X(r, c) * Y(r, c): sum(X % Y, 0), accumulator dtype. */
+int fx_colsum_xy(fx_dtype dt, const void* X, const void* Y, void* out, fx_shape shape,
+                 void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream);
+
+/* ---- unfused baseline: one kernel per operator ---------------------------
+ * The same skeletons and launch configurations as the fused calls, but each
+ * operator writes a full temporary, as toolkits without fusion do (Sec. 4). */
+
+/* out = op(A), op in NEG/ABS/EXP/SQRT (ABS/NEG also for U32? no: FP only). */
+int fx_op_unary(int op, fx_dtype dt, const void* A, void* out, int64_t n,
+                const fx_launch* cfg, void* stream);
+
+/* out = A op B, op in ADD/SUB/SCHUR/DIV (FP) or ADD/SUB/SCHUR/XOR (U32). */
+int fx_op_binary(int op, fx_dtype dt, const void* A, const void* B, void* out,
+                 int64_t n, const fx_launch* cfg, void* stream);
+
+/* out = scalar op with k (FX_OP_S*), k rounded to the compute type
+ * (for U32 it must be an integer in [0, 2^32)). */
+int fx_op_scalar(int op, fx_dtype dt, const void* A, double k, void* out, int64_t n,
+                 const fx_launch* cfg, void* stream);
+
+/* A reduction of materialised arrays: ACCU/COLSUM/ROWSUM/NORM of A, or DOT
+ * of A and B.  Output as for the fused calls (FP64 scalar, or accumulator
+ * dtype vector). */
+int fx_reduce(int kind, fx_dtype dt, const void* A, const void* B, fx_shape shape,
+              void* out, void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream);
+
+/* Bytes of temporaries that fx_unfused(expr) needs. */
+size_t fx_unfused_tmp_bytes(int expr, fx_dtype dt, fx_shape shape);
+
+/* The workload expression `expr` (FX_EXPR_*) evaluated one operator at a
+ * time with caller-provided temporaries `tmp` (fx_unfused_tmp_bytes bytes),
+ * enqueuing one fx_op_* / fx_reduce kernel per AST node.  inputs = {X, Y, W}
+ * as the expression needs; `a` is the scalar of FX_EXPR_AXY_EXPW. */
+int fx_unfused(int expr, fx_dtype dt, const void* const* inputs, double a, void* out,
+               fx_shape shape, void* tmp, size_t tmp_bytes, void* ws, size_t ws_bytes,
+               const fx_launch* cfg, void* stream);
+
+/* ---- measurement kernels ------------------------------------------------- */
+
+/* dst[i] = src[i] for `bytes` bytes (16-byte aligned, multiple of 16): the
+ * achievable-bandwidth ceiling (Sec. 4 measures it with a copy benchmark). */
+int fx_bw_copy(const void* src, void* dst, size_t bytes, const fx_launch* cfg,
+               void* stream);
+
+/* Streams `bytes` bytes of src into a per-block sum written to sink (one
+ * double per block; sink holds at least `split` doubles): read ceiling. */
+int fx_bw_read(const void* src, size_t bytes, double* sink, const fx_launch* cfg,
+               void* stream);
+
+/* dst[i] = value for `bytes` bytes: write ceiling and cache flushing. */
+int fx_bw_write(void* dst, size_t bytes, uint32_t value, const fx_launch* cfg,
+                void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FX_H */

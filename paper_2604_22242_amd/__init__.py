@@ -1,0 +1,310 @@
+"""Python binding of libfx.so, the fused element-wise expression library for
+MI355X (gfx950).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name in ``include/fx.h``.  Tensors are torch tensors on a ROCm
+device (their data pointers are passed through); the stream defaults to
+torch's current stream.  There is no fallback: if the HIP library is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfx.so")
+
+F32, F64, BF16, F16, U32 = 0, 1, 2, 3, 4
+R_ACCU, R_COLSUM, R_ROWSUM, R_NORM, R_DOT = 1, 2, 3, 4, 5
+OP = {"neg": 1, "abs": 2, "exp": 3, "sqrt": 4, "add": 10, "sub": 11, "schur": 12, "div": 13,
+      "xor": 14, "sadd": 20, "smul": 21, "sdiv": 22, "srdiv": 23, "ssub": 24, "srsub": 25}
+EXPR = {"c1_z": 1, "accu_xy": 2, "c2_z": 3, "c2_colsum": 4, "c2_rowsum": 5, "norm_diff": 6,
+        "colsum_xy": 7, "axy_expw": 8}
+STATUS = {0: "FX_OK", 1: "FX_E_ARG", 2: "FX_E_SHAPE", 3: "FX_E_DTYPE", 4: "FX_E_WORKSPACE",
+          5: "FX_E_HIP", 6: "FX_E_UNSUPPORTED", 7: "FX_E_CONFIG"}
+
+
+class FxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("ept", ctypes.c_int32),
+                ("vec_bytes", ctypes.c_int32), ("split", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.ept, self.vec_bytes, self.split)
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_D = ctypes.c_double
+_LP = ctypes.POINTER(Launch)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "fx_version": (ctypes.c_char_p, []),
+    "fx_last_error": (ctypes.c_char_p, []),
+    "fx_synchronize": (_I, [_P]),
+    "fx_workspace_bytes": (_SZ, [_I, _I, Shape, _LP]),
+    "fx_resolve_launch": (_I, [_I, _I, Shape, _LP, _LP]),
+    "fx_c1_z": (_I, [_I, _P, _P, _P, _P, _I64, _LP, _P]),
+    "fx_axy_expw": (_I, [_I, _D, _P, _P, _P, _P, _I64, _LP, _P]),
+    "fx_accu_xy": (_I, [_I, _P, _P, _I64, _P, _P, _SZ, _LP, _P]),
+    "fx_dot": (_I, [_I, _P, _P, _I64, _P, _P, _SZ, _LP, _P]),
+    "fx_c2_z": (_I, [_I, _P, _P, _P, _P, Shape, _LP, _P]),
+    "fx_c2_colsum": (_I, [_I, _P, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
+    "fx_c2_rowsum": (_I, [_I, _P, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
+    "fx_norm_fro_diff": (_I, [_I, _P, _P, Shape, _P, _P, _SZ, _LP, _P]),
+    "fx_colsum_xy": (_I, [_I, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
+    "fx_op_unary": (_I, [_I, _I, _P, _P, _I64, _LP, _P]),
+    "fx_op_binary": (_I, [_I, _I, _P, _P, _P, _I64, _LP, _P]),
+    "fx_op_scalar": (_I, [_I, _I, _P, _D, _P, _I64, _LP, _P]),
+    "fx_reduce": (_I, [_I, _I, _P, _P, Shape, _P, _P, _SZ, _LP, _P]),
+    "fx_unfused_tmp_bytes": (_SZ, [_I, _I, Shape]),
+    "fx_unfused": (_I, [_I, _I, ctypes.POINTER(_P), _D, _P, Shape, _P, _SZ, _P, _SZ, _LP, _P]),
+    "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
+    "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
+    "fx_bw_write": (_I, [_P, _SZ, ctypes.c_uint32, _LP, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libfx.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FxError(-1, "%s is missing: run paper_2604_22242_amd.build first" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+# ---- marshalling helpers ----------------------------------------------------
+
+
+def dtype_code(t) -> int:
+    import torch
+    m = {torch.float32: F32, torch.float64: F64, torch.bfloat16: BF16, torch.float16: F16,
+         torch.uint32: U32, torch.int32: U32}
+    try:
+        return m[t.dtype]
+    except KeyError:
+        raise FxError(3, "unsupported tensor dtype %s" % t.dtype) from None
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _cfg(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, Launch):
+        return ctypes.pointer(cfg)
+    if isinstance(cfg, dict):
+        cfg = (cfg.get("block", 0), cfg.get("ept", 0), cfg.get("vec_bytes", 0), cfg.get("split", 0))
+    return ctypes.pointer(Launch(*cfg))
+
+
+def _shape(s):
+    if isinstance(s, Shape):
+        return s
+    return Shape(int(s[0]), int(s[1]))
+
+
+def check(rc):
+    if rc != 0:
+        raise FxError(rc, lib().fx_last_error().decode())
+    return rc
+
+
+def _shape_of(t, shape):
+    if shape is not None:
+        return _shape(shape)
+    if t.dim() == 2:  # a column-major matrix is handed over as its transpose's storage
+        return Shape(t.shape[0], t.shape[1])
+    return Shape(t.numel(), 1)
+
+
+# ---- library ------------------------------------------------------------------
+
+
+def fx_version() -> str:
+    return lib().fx_version().decode()
+
+
+def fx_last_error() -> str:
+    return lib().fx_last_error().decode()
+
+
+def fx_synchronize(stream=None):
+    return check(lib().fx_synchronize(_stream(stream)))
+
+
+def fx_workspace_bytes(kind, dt, shape, cfg=None) -> int:
+    return lib().fx_workspace_bytes(kind, dt, _shape(shape), _cfg(cfg))
+
+
+def fx_resolve_launch(kind, dt, shape, cfg=None) -> tuple:
+    out = Launch()
+    check(lib().fx_resolve_launch(kind, dt, _shape(shape), _cfg(cfg), ctypes.pointer(out)))
+    return out.as_tuple()
+
+
+def workspace(kind, dt, shape, cfg=None, device=None):
+    """A zero-filled device workspace for reduction `kind` (None if none is
+    needed)."""
+    import torch
+    nb = fx_workspace_bytes(kind, dt, shape, cfg)
+    if nb == 0:
+        return None
+    return torch.zeros(nb, dtype=torch.uint8, device=device or "cuda")
+
+
+def _ws(ws):
+    if ws is None:
+        return None, 0
+    return ws.data_ptr(), ws.numel() * ws.element_size()
+
+
+# ---- fused entry points -----------------------------------------------------------
+
+
+def fx_c1_z(X, Y, W, Z, cfg=None, stream=None, n=None):
+    n = X.numel() if n is None else n
+    return check(lib().fx_c1_z(dtype_code(X), _ptr(X), _ptr(Y), _ptr(W), _ptr(Z), n, _cfg(cfg),
+                               _stream(stream)))
+
+
+def fx_axy_expw(a, X, Y, W, Z, cfg=None, stream=None, n=None):
+    n = X.numel() if n is None else n
+    return check(lib().fx_axy_expw(dtype_code(X), float(a), _ptr(X), _ptr(Y), _ptr(W), _ptr(Z),
+                                   n, _cfg(cfg), _stream(stream)))
+
+
+def fx_accu_xy(X, Y, out, ws=None, cfg=None, stream=None, n=None):
+    n = X.numel() if n is None else n
+    p, nb = _ws(ws)
+    return check(lib().fx_accu_xy(dtype_code(X), _ptr(X), _ptr(Y), n, _ptr(out), p, nb,
+                                  _cfg(cfg), _stream(stream)))
+
+
+def fx_dot(X, Y, out, ws=None, cfg=None, stream=None, n=None):
+    n = X.numel() if n is None else n
+    p, nb = _ws(ws)
+    return check(lib().fx_dot(dtype_code(X), _ptr(X), _ptr(Y), n, _ptr(out), p, nb, _cfg(cfg),
+                              _stream(stream)))
+
+
+def fx_c2_z(X, Y, W, Z, shape, cfg=None, stream=None):
+    return check(lib().fx_c2_z(dtype_code(X), _ptr(X), _ptr(Y), _ptr(W), _ptr(Z), _shape(shape),
+                               _cfg(cfg), _stream(stream)))
+
+
+def fx_c2_colsum(X, Y, W, out, shape, ws=None, cfg=None, stream=None):
+    p, nb = _ws(ws)
+    return check(lib().fx_c2_colsum(dtype_code(X), _ptr(X), _ptr(Y), _ptr(W), _ptr(out),
+                                    _shape(shape), p, nb, _cfg(cfg), _stream(stream)))
+
+
+def fx_c2_rowsum(X, Y, W, out, shape, ws=None, cfg=None, stream=None):
+    p, nb = _ws(ws)
+    return check(lib().fx_c2_rowsum(dtype_code(X), _ptr(X), _ptr(Y), _ptr(W), _ptr(out),
+                                    _shape(shape), p, nb, _cfg(cfg), _stream(stream)))
+
+
+def fx_norm_fro_diff(X, Y, out, shape, ws=None, cfg=None, stream=None):
+    p, nb = _ws(ws)
+    return check(lib().fx_norm_fro_diff(dtype_code(X), _ptr(X), _ptr(Y), _shape(shape),
+                                        _ptr(out), p, nb, _cfg(cfg), _stream(stream)))
+
+
+def fx_colsum_xy(X, Y, out, shape, ws=None, cfg=None, stream=None):
+    p, nb = _ws(ws)
+    return check(lib().fx_colsum_xy(dtype_code(X), _ptr(X), _ptr(Y), _ptr(out), _shape(shape),
+                                    p, nb, _cfg(cfg), _stream(stream)))
+
+
+# ---- unfused baseline -----------------------------------------------------------------
+
+
+def fx_op_unary(op, A, out, cfg=None, stream=None):
+    return check(lib().fx_op_unary(OP.get(op, op), dtype_code(A), _ptr(A), _ptr(out), A.numel(),
+                                   _cfg(cfg), _stream(stream)))
+
+
+def fx_op_binary(op, A, B, out, cfg=None, stream=None):
+    return check(lib().fx_op_binary(OP.get(op, op), dtype_code(A), _ptr(A), _ptr(B), _ptr(out),
+                                    A.numel(), _cfg(cfg), _stream(stream)))
+
+
+def fx_op_scalar(op, A, k, out, cfg=None, stream=None):
+    return check(lib().fx_op_scalar(OP.get(op, op), dtype_code(A), _ptr(A), float(k), _ptr(out),
+                                    A.numel(), _cfg(cfg), _stream(stream)))
+
+
+def fx_reduce(kind, A, B, out, shape, ws=None, cfg=None, stream=None):
+    p, nb = _ws(ws)
+    return check(lib().fx_reduce(kind, dtype_code(A), _ptr(A), _ptr(B), _shape(shape), _ptr(out),
+                                 p, nb, _cfg(cfg), _stream(stream)))
+
+
+def fx_unfused_tmp_bytes(expr, dt, shape) -> int:
+    return lib().fx_unfused_tmp_bytes(EXPR.get(expr, expr), dt, _shape(shape))
+
+
+def fx_unfused(expr, inputs, out, shape, tmp, ws=None, a=0.0, cfg=None, stream=None):
+    arr = (_P * 3)(*[_ptr(t) for t in inputs] + [None] * (3 - len(inputs)))
+    p, nb = _ws(ws)
+    tp, tb = _ws(tmp)
+    return check(lib().fx_unfused(EXPR.get(expr, expr), dtype_code(inputs[0]), arr, float(a),
+                                  _ptr(out), _shape(shape), tp, tb, p, nb, _cfg(cfg),
+                                  _stream(stream)))
+
+
+# ---- measurement kernels ------------------------------------------------------------
+
+
+def fx_bw_copy(src, dst, nbytes, cfg=None, stream=None):
+    return check(lib().fx_bw_copy(_ptr(src), _ptr(dst), nbytes, _cfg(cfg), _stream(stream)))
+
+
+def fx_bw_read(src, nbytes, sink, cfg=None, stream=None):
+    return check(lib().fx_bw_read(_ptr(src), nbytes, _ptr(sink), _cfg(cfg), _stream(stream)))
+
+
+def fx_bw_write(dst, nbytes, value=0, cfg=None, stream=None):
+    return check(lib().fx_bw_write(_ptr(dst), nbytes, value, _cfg(cfg), _stream(stream)))

@@ -1,0 +1,77 @@
+"""Build libfx.so for gfx950 with hipcc (one object per source, in parallel).
+
+    python -m paper_2604_22242_amd.build [--jobs N]
+
+Flags: -O3, no fast-math (IEEE divide/sqrt and denormals kept), packed FP32
+instructions disabled on the device (-target-feature -packed-fp32-ops).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import glob
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+OBJ = os.path.join(ROOT, "_build", "obj")
+LIB = os.path.join(HERE, "libfx.so")
+ARCH = os.environ.get("FX_OFFLOAD_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+
+
+def _compile(src: str, extra: list[str], objdir: str) -> tuple[str, float]:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    t = time.time()
+    cmd = [HIPCC] + CFLAGS + extra + ["-c", src, "-o", obj]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    # the host pass does not know the device-only feature name: drop that line
+    err = "\n".join(l for l in (p.stderr or "").splitlines()
+                    if "not a recognized feature for this target" not in l)
+    if p.returncode != 0:
+        raise RuntimeError("hipcc failed on %s:\n%s" % (src, err))
+    if err.strip():
+        sys.stderr.write(err + "\n")
+    return obj, time.time() - t
+
+
+def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool = False,
+          out: str | None = None) -> str:
+    """Compile every csrc/*.hip and link `out` (default: the package's
+    libfx.so).  `extra` adds hipcc flags (e.g. -D overrides)."""
+    out = out or LIB
+    objdir = OBJ if out == LIB else os.path.join(ROOT, "_build", "obj_" + os.path.basename(out))
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    extra = extra or []
+    objs = []
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        for obj, dt in ex.map(lambda s: _compile(s, extra, objdir), srcs):
+            objs.append(obj)
+            if verbose:
+                print("  %-40s %6.1fs" % (os.path.basename(obj), dt), flush=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("link failed:\n" + p.stderr)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    a = ap.parse_args()
+    t = time.time()
+    print(build(a.jobs, verbose=True), "%.1fs" % (time.time() - t))
