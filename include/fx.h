@@ -97,7 +97,9 @@ typedef enum {
   FX_OP_SDIV = 22,  /* A / k */
   FX_OP_SRDIV = 23, /* k / A */
   FX_OP_SSUB = 24,  /* A - k */
-  FX_OP_SRSUB = 25  /* k - A */
+  FX_OP_SRSUB = 25, /* k - A */
+  FX_OP_LEAF = 30,  /* tape node: an input array     */
+  FX_OP_CONST = 31  /* tape node: a scalar constant  */
 } fx_op;
 
 /* The workload expressions, for fx_unfused() and fx_workspace_bytes(). */
@@ -220,6 +222,94 @@ size_t fx_unfused_tmp_bytes(int expr, fx_dtype dt, fx_shape shape);
 int fx_unfused(int expr, fx_dtype dt, const void* const* inputs, double a, void* out,
                fx_shape shape, void* tmp, size_t tmp_bytes, void* ws, size_t ws_bytes,
                const fx_launch* cfg, void* stream);
+
+/* ---- run-time expression tapes ------------------------------------------
+ * For trees only known at run time (they cannot be C++ types).  The tree is
+ * compiled on the host into a short register program that one kernel
+ * interprets per element; the element loop and the reductions are the same
+ * skeletons as the fused calls, so a tape is also read once and written
+ * once.  Operators: FX_OP_ADD/SUB/SCHUR/DIV (binary), FX_OP_NEG/ABS/EXP/SQRT
+ * (unary), FX_OP_LEAF and FX_OP_CONST (leaves).  Floating-point dtypes. */
+
+/* One node.  Nodes are listed children first and the last node is the root;
+ * a node may be the operand of several later nodes (a DAG is accepted). */
+typedef struct {
+  int32_t op;    /* FX_OP_* above */
+  int32_t a, b;  /* operand node indices (< this node's index); -1 if unused */
+  int32_t input; /* FX_OP_LEAF: which input array (0..3) */
+  double value;  /* FX_OP_CONST: the constant, rounded to the compute type */
+} fx_node;
+
+/* Structural features of a compiled tape (also the cost model's inputs). */
+typedef struct {
+  int32_t n_nodes, n_inputs, depth, n_instructions, n_slots, n_consts;
+  int32_t op_count[8]; /* add, sub, schur, div, neg, abs, exp, sqrt */
+} fx_tape_info;
+
+typedef struct fx_tape fx_tape;
+
+/* Compile nodes[0..n_nodes) into *out (library-owned; fx_tape_destroy frees
+ * it).  Limits: 4 inputs, 128 instructions, 12 live slots (FX_E_UNSUPPORTED
+ * beyond them); malformed trees give FX_E_ARG. */
+int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out);
+void fx_tape_destroy(fx_tape* t);
+int fx_tape_describe(const fx_tape* t, fx_tape_info* out);
+
+/* Evaluate tape t over inputs[0..n_inputs) (n_inputs >= the tape's inputs,
+ * all of storage dtype dt and shape `shape`).  kind 0: element-wise, `out`
+ * has the storage dtype; FX_R_ACCU / FX_R_NORM: one double; FX_R_COLSUM /
+ * FX_R_ROWSUM: accumulator dtype vector.  ws as for the fused reductions
+ * (fx_workspace_bytes of the same kind). */
+int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                 fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
+                 const fx_launch* cfg, void* stream);
+
+/* ---- batches: thousands of uneven expressions in one launch -------------
+ * Every expression of a batch is a compiled tape over vectors.  The batch is
+ * cut into fixed-size tiles (the tiles of one expression are consecutive);
+ * one persistent kernel walks the tile table and runs each tile's program,
+ * and the last tile of a reducing expression to finish adds its tile
+ * partials in tile order (FP64), so each result is independent of the other
+ * expressions and of their order in the batch.  The launch can be captured
+ * once in a HIP graph and replayed. */
+
+typedef struct {
+  const fx_tape* tape;      /* compiled tree (not retained after create) */
+  const void* inputs[4];    /* device inputs, n elements each, as the tape reads */
+  void* out;                /* kind 0: n elements of the storage dtype;
+                               FX_R_ACCU: one double */
+  int64_t n;                /* elements (a vector of length n) */
+  int32_t kind;             /* 0 (element-wise) or FX_R_ACCU */
+  int32_t reserved;
+} fx_batch_item;
+
+typedef struct {
+  int32_t count, block, ept, vec_bytes, grid;
+  int64_t n_tiles, tile_elems;
+  int64_t bytes; /* algorithmic bytes: inputs read once + element-wise outputs */
+} fx_batch_info;
+
+typedef struct fx_batch fx_batch;
+
+/* Build a batch (synchronous: allocates and uploads its device tables, owned
+ * by the batch).  cfg: block / ept / vec_bytes as elsewhere, split = grid of
+ * the persistent kernel (0 = 8 blocks per CU); tile_elems: elements per tile
+ * (0 = 16384; rounded up to whole block passes).  Item pointers must stay
+ * valid while the batch is used. */
+int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt,
+                    const fx_launch* cfg, int64_t tile_elems, fx_batch** out);
+
+/* Enqueue the whole batch as one kernel launch on `stream`. */
+int fx_batch_launch(fx_batch* b, void* stream);
+
+/* First call: capture the launch on `stream` into a HIP graph and launch it;
+ * later calls: replay the graph on `stream` (one hipGraphLaunch). */
+int fx_batch_graph(fx_batch* b, void* stream);
+
+int fx_batch_describe(const fx_batch* b, fx_batch_info* out);
+
+/* Frees the batch's device tables and graph (synchronises its last stream). */
+void fx_batch_destroy(fx_batch* b);
 
 /* ---- measurement kernels ------------------------------------------------- */
 

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(HERE, "libfx.so")
 F32, F64, BF16, F16, U32 = 0, 1, 2, 3, 4
 R_ACCU, R_COLSUM, R_ROWSUM, R_NORM, R_DOT = 1, 2, 3, 4, 5
 OP = {"neg": 1, "abs": 2, "exp": 3, "sqrt": 4, "add": 10, "sub": 11, "schur": 12, "div": 13,
-      "xor": 14, "sadd": 20, "smul": 21, "sdiv": 22, "srdiv": 23, "ssub": 24, "srsub": 25}
+      "xor": 14, "sadd": 20, "smul": 21, "sdiv": 22, "srdiv": 23, "ssub": 24, "srsub": 25,
+      "leaf": 30, "const": 31}
+NODE_OP = dict(OP, mul=OP["schur"])  # tree nodes name the Schur product "mul"
 EXPR = {"c1_z": 1, "accu_xy": 2, "c2_z": 3, "c2_colsum": 4, "c2_rowsum": 5, "norm_diff": 6,
         "colsum_xy": 7, "axy_expw": 8}
 STATUS = {0: "FX_OK", 1: "FX_E_ARG", 2: "FX_E_SHAPE", 3: "FX_E_DTYPE", 4: "FX_E_WORKSPACE",
@@ -41,6 +43,39 @@ class Launch(ctypes.Structure):
 
 class Shape(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64)]
+
+
+class Node(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("input", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class TapeInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_inputs", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("n_instructions", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("n_consts", ctypes.c_int32),
+                ("op_count", ctypes.c_int32 * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "op_count"}
+        d["op_count"] = list(self.op_count)
+        return d
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("tape", ctypes.c_void_p), ("inputs", ctypes.c_void_p * 4),
+                ("out", ctypes.c_void_p), ("n", ctypes.c_int64), ("kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("block", ctypes.c_int32), ("ept", ctypes.c_int32),
+                ("vec_bytes", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("n_tiles", ctypes.c_int64), ("tile_elems", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _P = ctypes.c_void_p
@@ -72,6 +107,17 @@ _SIGS = {
     "fx_reduce": (_I, [_I, _I, _P, _P, Shape, _P, _P, _SZ, _LP, _P]),
     "fx_unfused_tmp_bytes": (_SZ, [_I, _I, Shape]),
     "fx_unfused": (_I, [_I, _I, ctypes.POINTER(_P), _D, _P, Shape, _P, _SZ, _P, _SZ, _LP, _P]),
+    "fx_tape_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "fx_tape_destroy": (None, [_P]),
+    "fx_tape_describe": (_I, [_P, ctypes.POINTER(TapeInfo)]),
+    "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
+                          _LP, _P]),
+    "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
+                             ctypes.POINTER(_P)]),
+    "fx_batch_launch": (_I, [_P, _P]),
+    "fx_batch_graph": (_I, [_P, _P]),
+    "fx_batch_describe": (_I, [_P, ctypes.POINTER(BatchInfo)]),
+    "fx_batch_destroy": (None, [_P]),
     "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
     "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
     "fx_bw_write": (_I, [_P, _SZ, ctypes.c_uint32, _LP, _P]),
@@ -293,6 +339,125 @@ def fx_unfused(expr, inputs, out, shape, tmp, ws=None, a=0.0, cfg=None, stream=N
     return check(lib().fx_unfused(EXPR.get(expr, expr), dtype_code(inputs[0]), arr, float(a),
                                   _ptr(out), _shape(shape), tp, tb, p, nb, _cfg(cfg),
                                   _stream(stream)))
+
+
+# ---- run-time tapes --------------------------------------------------------------------
+
+
+def nodes_array(nodes):
+    """Tree nodes (op, a, b, input, value), children first, as fx_node[]."""
+    arr = (Node * len(nodes))()
+    for i, (op, a, b, inp, val) in enumerate(nodes):
+        arr[i] = Node(NODE_OP[op] if isinstance(op, str) else op, a, b, inp, val)
+    return arr
+
+
+class Tape:
+    """An fx_tape handle (compiled on creation, destroyed with the object)."""
+
+    def __init__(self, nodes):
+        self.handle = ctypes.c_void_p()
+        arr = nodes_array(nodes)
+        check(lib().fx_tape_create(arr, len(nodes), ctypes.byref(self.handle)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fx_tape_destroy(self.handle)
+            self.handle = None
+
+    def info(self) -> dict:
+        return fx_tape_describe(self)
+
+
+def fx_tape_create(nodes) -> Tape:
+    return Tape(nodes)
+
+
+def fx_tape_destroy(tape: Tape):
+    if tape.handle:
+        lib().fx_tape_destroy(tape.handle)
+        tape.handle = None
+
+
+def fx_tape_describe(tape: Tape) -> dict:
+    info = TapeInfo()
+    check(lib().fx_tape_describe(tape.handle, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stream=None,
+                 dt=None):
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    if dt is None:
+        dt = dtype_code(inputs[0]) if inputs else dtype_code(out)
+    p, nb = _ws(ws)
+    return check(lib().fx_tape_eval(tape.handle, dt, arr, len(inputs), _shape(shape), kind,
+                                    _ptr(out), p, nb, _cfg(cfg), _stream(stream)))
+
+
+# ---- batches ----------------------------------------------------------------------------
+
+
+class Batch:
+    """An fx_batch handle.  items: (tape, [inputs], out, n, kind) tuples; the
+    tensors must stay alive while the batch is used (the binding keeps
+    references to them)."""
+
+    def __init__(self, items, dt, cfg=None, tile_elems=0):
+        arr = (BatchItem * max(1, len(items)))()
+        self._keep = []
+        for i, (tape, ins, out, n, kind) in enumerate(items):
+            bi = BatchItem()
+            bi.tape = tape.handle
+            for q, t in enumerate(ins):
+                bi.inputs[q] = _ptr(t)
+            bi.out = _ptr(out)
+            bi.n = int(n)
+            bi.kind = int(kind)
+            arr[i] = bi
+            self._keep.append((tape, ins, out))
+        self.handle = ctypes.c_void_p()
+        check(lib().fx_batch_create(arr, len(items), dt, _cfg(cfg), int(tile_elems),
+                                    ctypes.byref(self.handle)))
+
+    def launch(self, stream=None):
+        return check(lib().fx_batch_launch(self.handle, _stream(stream)))
+
+    def graph(self, stream=None):
+        return check(lib().fx_batch_graph(self.handle, _stream(stream)))
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        check(lib().fx_batch_describe(self.handle, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def destroy(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fx_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def fx_batch_create(items, dt, cfg=None, tile_elems=0) -> Batch:
+    return Batch(items, dt, cfg, tile_elems)
+
+
+def fx_batch_launch(batch: Batch, stream=None):
+    return batch.launch(stream)
+
+
+def fx_batch_graph(batch: Batch, stream=None):
+    return batch.graph(stream)
+
+
+def fx_batch_describe(batch: Batch) -> dict:
+    return batch.info()
+
+
+def fx_batch_destroy(batch: Batch):
+    batch.destroy()
 
 
 # ---- measurement kernels ------------------------------------------------------------

@@ -1,0 +1,321 @@
+// Batches: one persistent launch over thousands of uneven expressions.
+//
+// Host: each item's compiled program is copied into a device array, the
+// items are cut into fixed-size tiles (consecutive per item) and a tile
+// table maps tile -> item.  Device: a grid of persistent blocks strides over
+// the tiles; the program of a tile is read through a pointer (wave-uniform
+// loads), interpreted with the same TapeExpr code as fx_tape_eval, and
+// element-wise tiles write their slice of the output.  Reducing items
+// publish one FP64 partial per tile; the tile that draws the item's last
+// ticket adds the item's partials in tile order and resets the counter.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "fx_tape.hpp"
+
+namespace fx {
+
+struct batch_desc {
+  const void* in[kTapeMaxIn];
+  void* out;
+  int64_t n;
+  int32_t kind;
+  int32_t n_tiles;
+  int64_t first_tile;
+};
+
+template <class T, int N, int EPT>
+__global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restrict__ descs,
+                                                   const tape_prog* __restrict__ progs,
+                                                   const uint32_t* __restrict__ tile_item,
+                                                   int64_t n_tiles, int64_t tile_elems,
+                                                   double* __restrict__ partials,
+                                                   unsigned* __restrict__ counters) {
+  using C = ct_t<T>;
+  __shared__ double lds[kMaxBlock / 64];
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint32_t it = tile_item[t];
+    const batch_desc d = descs[it];
+    TapeExpr<T, true> x;
+#pragma unroll
+    for (int q = 0; q < kTapeMaxIn; ++q) x.p[q] = static_cast<const T*>(d.in[q]);
+    x.n_rows = d.n;
+    x.n_cols = 1;
+    x.prog = progs + it;
+    const int64_t i0 = (t - d.first_tile) * tile_elems;
+    const int64_t i1 = min(d.n, i0 + tile_elems);
+    const int64_t nvec = (i1 - i0) / N;  // i0 is a multiple of N
+    const int64_t step = (int64_t)blockDim.x * EPT;
+    if (d.kind == 0) {
+      T* z = static_cast<T*>(d.out);
+      for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += step) {
+        if (v0 - threadIdx.x + step <= nvec) {
+          lanes<C, N> r[EPT];
+          eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) store_lanes<N, kNTS>(z, i0 + (v0 + k * blockDim.x) * N, r[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) {
+            const int64_t v = v0 + k * blockDim.x;
+            if (v < nvec) store_lanes<N, kNTS>(z, i0 + v * N, x.template at_vec<N, kNT>(i0 + v * N));
+          }
+        }
+      }
+      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x)
+        z[i] = static_cast<T>(x.at(i));
+    } else {
+      accum<C> acc;
+      for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += step) {
+        if (v0 - threadIdx.x + step <= nvec) {
+          lanes<C, N> r[EPT];
+          eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
+#pragma unroll
+          for (int k = 0; k < EPT; ++k)
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc.add(r[k].v[j]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) {
+            const int64_t v = v0 + k * blockDim.x;
+            if (v < nvec) {
+              lanes<C, N> r = x.template at_vec<N, kNT>(i0 + v * N);
+#pragma unroll
+              for (int j = 0; j < N; ++j) acc.add(r.v[j]);
+            }
+          }
+        }
+      }
+      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x) acc.add(x.at(i));
+      const double s = block_sum<double>(acc.value(), lds);
+      if (d.n_tiles == 1) {
+        if (threadIdx.x == 0) *static_cast<double*>(d.out) = s;
+      } else {
+        if (threadIdx.x == 0) publish(partials + t, s);
+        if (take_last_ticket(counters + it, d.n_tiles)) {
+          if (threadIdx.x == 0) {
+            *static_cast<double*>(d.out) = sum_strided<double>(partials + d.first_tile, 1, d.n_tiles);
+            reset_counter(counters + it);
+          }
+        }
+      }
+    }
+    __syncthreads();  // the next tile reuses lds
+  }
+}
+
+}  // namespace fx
+
+using namespace fx;
+
+struct fx_batch {
+  fx_dtype dt;
+  fx_batch_info info;
+  batch_desc* d_descs = nullptr;
+  tape_prog* d_progs = nullptr;
+  uint32_t* d_tiles = nullptr;
+  double* d_partials = nullptr;
+  unsigned* d_counters = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last_stream = nullptr;
+  int vec;
+};
+
+static void batch_free(fx_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  hipFree(b->d_descs);
+  hipFree(b->d_progs);
+  hipFree(b->d_tiles);
+  hipFree(b->d_partials);
+  hipFree(b->d_counters);
+}
+
+static int elem_of(fx_dtype dt) {
+  switch (dt) {
+    case FX_F32: return 4;
+    case FX_F64: return 8;
+    case FX_BF16: case FX_F16: return 2;
+    default: return 0;
+  }
+}
+
+template <class F> static int batch_dispatch(fx_dtype dt, int vec, int ept, F&& f) {
+  return with_fp(dt, [&](auto tg) {
+    using T = typename decltype(tg)::type;
+    return with_vec<T>(vec, [&](auto Nc) {
+      return with_ept<2>(ept, [&](auto Ec) {
+        return f(tag<T>{}, Nc, Ec);
+      });
+    });
+  });
+}
+
+static int batch_run(fx_batch* b, hipStream_t st) {
+  const fx_batch_info& I = b->info;
+  if (I.n_tiles == 0) return FX_OK;
+  return batch_dispatch(b->dt, b->vec, I.ept, [&](auto tg, auto Nc, auto Ec) {
+    using T = typename decltype(tg)::type;
+    constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
+    hipLaunchKernelGGL((k_batch<T, N, EPT>), dim3(I.grid), dim3(I.block), 0, st, b->d_descs,
+                       b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems, b->d_partials,
+                       b->d_counters);
+    return hip_check(hipGetLastError(), "k_batch launch");
+  });
+}
+
+extern "C" {
+
+int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, const fx_launch* cfg,
+                    int64_t tile_elems, fx_batch** out) {
+  if (!out) return fail(FX_E_ARG, "NULL output handle");
+  *out = nullptr;
+  const int elem = elem_of(dt);
+  if (!elem) return fail(FX_E_DTYPE, "batches evaluate floating-point dtypes only");
+  if (count < 0 || (count > 0 && !items)) return fail(FX_E_ARG, "bad item list");
+  if (int rc = check_launch(cfg)) return rc;
+  if (tile_elems < 0) return fail(FX_E_ARG, "negative tile size");
+  fx_launch c = cfg ? *cfg : fx_launch{0, 0, 0, 0};
+  uintptr_t addr_or = 0;
+  for (int i = 0; i < count; ++i) {
+    const fx_batch_item& it = items[i];
+    if (!it.tape) return fail(FX_E_ARG, "item %d: NULL tape", i);
+    if (it.n < 0) return fail(FX_E_ARG, "item %d: negative size", i);
+    if (it.kind != 0 && it.kind != FX_R_ACCU) return fail(FX_E_ARG, "item %d: kind %d", i, it.kind);
+    if (it.n > 0 && !it.out) return fail(FX_E_ARG, "item %d: NULL output", i);
+    if (it.kind == FX_R_ACCU && !it.out) return fail(FX_E_ARG, "item %d: NULL output", i);
+    for (int q = 0; q < it.tape->prog.n_in; ++q) {
+      if (it.n > 0 && !it.inputs[q]) return fail(FX_E_ARG, "item %d: NULL input %d", i, q);
+      addr_or |= reinterpret_cast<uintptr_t>(it.inputs[q]);
+    }
+    if (it.kind == 0) addr_or |= reinterpret_cast<uintptr_t>(it.out);
+  }
+  fx_batch* b = new (std::nothrow) fx_batch;
+  if (!b) return fail(FX_E_ARG, "out of host memory");
+  b->dt = dt;
+  fx_batch_info& I = b->info;
+  I = fx_batch_info{};
+  I.count = count;
+  I.block = c.block ? c.block : 256;
+  I.ept = c.ept ? c.ept : 1;
+  I.vec_bytes = (c.vec_bytes ? std::max(c.vec_bytes, elem) : 16);
+  if (addr_or & 15) I.vec_bytes = elem;  // every pointer must be 16-byte aligned for vectors
+  b->vec = I.vec_bytes / elem;
+  const int64_t pass = (int64_t)I.block * I.ept * b->vec;
+  const int64_t want = tile_elems ? tile_elems : 16384;
+  I.tile_elems = ceil_div(want, pass) * pass;
+  // tile table
+  std::vector<batch_desc> descs(count);
+  std::vector<tape_prog> progs(count);
+  std::vector<uint32_t> tiles;
+  int64_t first = 0;
+  for (int i = 0; i < count; ++i) {
+    const fx_batch_item& it = items[i];
+    batch_desc& d = descs[i];
+    for (int q = 0; q < kTapeMaxIn; ++q) d.in[q] = q < it.tape->prog.n_in ? it.inputs[q] : nullptr;
+    d.out = it.out;
+    d.n = it.n;
+    d.kind = it.kind;
+    const int64_t nt = std::max<int64_t>(1, ceil_div(it.n, I.tile_elems));  // accu of n=0 writes 0
+    if (it.kind == 0 && it.n == 0) {
+      d.n_tiles = 0;
+      d.first_tile = first;
+      progs[i] = it.tape->prog;
+      continue;
+    }
+    d.n_tiles = (int32_t)nt;
+    d.first_tile = first;
+    for (int64_t k = 0; k < nt; ++k) tiles.push_back((uint32_t)i);
+    first += nt;
+    progs[i] = it.tape->prog;
+    I.bytes += (int64_t)elem * it.n * (it.tape->prog.n_in + (it.kind == 0 ? 1 : 0));
+  }
+  I.n_tiles = first;
+  const int64_t grid_default = (int64_t)device_cus() * 8;
+  I.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(c.split ? c.split : grid_default,
+                                                          std::max<int64_t>(1, I.n_tiles)));
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMalloc(p, bytes);
+  };
+  alloc((void**)&b->d_descs, sizeof(batch_desc) * std::max(1, count));
+  alloc((void**)&b->d_progs, sizeof(tape_prog) * std::max(1, count));
+  alloc((void**)&b->d_tiles, sizeof(uint32_t) * std::max<int64_t>(1, I.n_tiles));
+  alloc((void**)&b->d_partials, sizeof(double) * std::max<int64_t>(1, I.n_tiles));
+  alloc((void**)&b->d_counters, sizeof(unsigned) * std::max(1, count));
+  if (e == hipSuccess && count)
+    e = hipMemcpy(b->d_descs, descs.data(), sizeof(batch_desc) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess && count)
+    e = hipMemcpy(b->d_progs, progs.data(), sizeof(tape_prog) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess && I.n_tiles)
+    e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint32_t) * I.n_tiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(unsigned) * std::max(1, count));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    int rc = hip_check(e, "fx_batch_create");
+    batch_free(b);
+    delete b;
+    return rc;
+  }
+  // reject configurations that are not compiled before anything is enqueued
+  int rc = batch_dispatch(dt, b->vec, I.ept, [](auto, auto, auto) { return FX_OK; });
+  if (rc != FX_OK) {
+    batch_free(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return FX_OK;
+}
+
+int fx_batch_launch(fx_batch* b, void* stream) {
+  if (!b) return fail(FX_E_ARG, "NULL batch");
+  b->last_stream = S(stream);
+  return batch_run(b, S(stream));
+}
+
+int fx_batch_graph(fx_batch* b, void* stream) {
+  if (!b) return fail(FX_E_ARG, "NULL batch");
+  hipStream_t st = S(stream);
+  if (!st) return fail(FX_E_ARG, "graph capture needs a non-default stream");
+  b->last_stream = st;
+  if (!b->exec) {
+    if (int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
+                           "hipStreamBeginCapture"))
+      return rc;
+    int rc = batch_run(b, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != FX_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (int rc2 = hip_check(e, "hipStreamEndCapture")) return rc2;
+    hipGraphExec_t x = nullptr;
+    if (int rc3 = hip_check(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+      hipGraphDestroy(g);
+      return rc3;
+    }
+    b->graph = g;
+    b->exec = x;
+  }
+  return hip_check(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
+}
+
+int fx_batch_describe(const fx_batch* b, fx_batch_info* out) {
+  if (!b || !out) return fail(FX_E_ARG, "NULL argument");
+  *out = b->info;
+  return FX_OK;
+}
+
+void fx_batch_destroy(fx_batch* b) {
+  if (!b) return;
+  if (b->last_stream) hipStreamSynchronize(b->last_stream);
+  else hipDeviceSynchronize();
+  batch_free(b);
+  delete b;
+}
+
+}  // extern "C"

@@ -42,6 +42,10 @@ struct leaf_info {
     else if (r != n_rows || c != n_cols) shape_ok = false;
     addr_or |= reinterpret_cast<uintptr_t>(p);
   }
+  void add_shape(int64_t r, int64_t c) {  // an expression without array leaves
+    if (n_rows < 0) { n_rows = r; n_cols = c; }
+    else if (r != n_rows || c != n_cols) shape_ok = false;
+  }
   bool aligned(int bytes) const { return (addr_or & (uintptr_t)(bytes - 1)) == 0; }
 };
 

@@ -100,8 +100,8 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
     } else {
       const int64_t target = cus * kColsumBlocksPerCU;
       int64_t s = c.split ? c.split : ceil_div(target, std::max<int64_t>(1, n_cols));
-      s = std::min<int64_t>(
-          s, std::max<int64_t>(1, ceil_div(n_rows, (int64_t)L.block * vec16 * L.ept)));
+      // every chunk holds at least one full pass of the block
+      s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n_rows, (int64_t)L.block * vec16)));
       L.split = (int)std::max<int64_t>(1, std::min<int64_t>(s, 65535));
     }
   } else {  // FX_R_ROWSUM

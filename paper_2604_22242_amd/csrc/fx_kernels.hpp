@@ -51,6 +51,16 @@ struct map_sq {
   __device__ static double finish(double s) { return ::sqrt(s); }
 };
 
+// EPT vectors of N elements at base, base + stride, ...: every leaf's loads
+// are issued before any arithmetic.  Expression types with their own
+// evaluation strategy (the run-time tape) overload this.
+template <int N, int EPT, class E>
+__device__ __forceinline__ void eval_tile(const E& e, int64_t base, int64_t stride,
+                                          lanes<typename E::ct, N> (&r)[EPT]) {
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(base + k * stride);
+}
+
 // ============================================================================
 // Element-wise: Z[i] = E(i), i < n.
 
@@ -64,8 +74,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ew(E e, T* __restrict__ z, int64_
     const int64_t v0 = t * tile + threadIdx.x;
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>((v0 + k * blockDim.x) * N);
+      eval_tile<N, EPT>(e, v0 * N, (int64_t)blockDim.x * N, r);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) store_lanes<N, kNTS>(z, (v0 + k * blockDim.x) * N, r[k]);
     } else {
@@ -99,8 +108,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_full(E e, int64_t n, typename wid
     const int64_t v0 = t * tile + threadIdx.x;
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>((v0 + k * blockDim.x) * N);
+      eval_tile<N, EPT>(e, v0 * N, (int64_t)blockDim.x * N, r);
 #pragma unroll
       for (int k = 0; k < EPT; ++k)
 #pragma unroll
@@ -164,8 +172,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_colsum(E e, int64_t n_rows, int s
     const int64_t v0 = t0 + threadIdx.x;
     if (t0 + tile <= nv) {
       lanes<C, N> r[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(base + (v0 + k * blockDim.x) * N);
+      eval_tile<N, EPT>(e, base + v0 * N, (int64_t)blockDim.x * N, r);
 #pragma unroll
       for (int k = 0; k < EPT; ++k)
 #pragma unroll
@@ -234,8 +241,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_rowsum(E e, int64_t n_rows, int64
     int64_t c = c0;
     for (; c + EPT <= c1; c += EPT) {
       lanes<C, N> r[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(r0 + (c + k) * n_rows);
+      eval_tile<N, EPT>(e, r0 + c * n_rows, n_rows, r);
 #pragma unroll
       for (int k = 0; k < EPT; ++k)
 #pragma unroll
@@ -281,14 +287,18 @@ __global__ __launch_bounds__(256) void k_fill_zero(O* out, int64_t n) {
 
 template <int V> using ic = std::integral_constant<int, V>;
 
-template <class F> inline int with_ept(int ept, F&& f) {
+// Largest EPT compiled for an expression type (the run-time tape keeps one
+// slot file per lane in registers and caps it lower).
+template <class E> struct max_ept { static constexpr int value = 8; };
+
+template <int MAX = 8, class F> inline int with_ept(int ept, F&& f) {
   switch (ept) {
     case 1: return f(ic<1>{});
-    case 2: return f(ic<2>{});
-    case 4: return f(ic<4>{});
-    case 8: return f(ic<8>{});
+    case 2: if constexpr (MAX >= 2) return f(ic<2>{}); break;
+    case 4: if constexpr (MAX >= 4) return f(ic<4>{}); break;
+    case 8: if constexpr (MAX >= 8) return f(ic<8>{}); break;
   }
-  return fail(FX_E_UNSUPPORTED, "ept %d not compiled (1, 2, 4, 8)", ept);
+  return fail(FX_E_UNSUPPORTED, "ept %d not compiled for this expression (max %d)", ept, MAX);
 }
 
 // Vector width in elements: one element (any alignment) or 16 bytes.
@@ -323,6 +333,11 @@ template <class E> int check_expr(const E& e, int64_t* n_rows, int64_t* n_cols) 
   return FX_OK;
 }
 
+// A defaulted EPT never exceeds what is compiled for the expression type.
+template <class E> inline void clamp_ept(launch& L, const fx_launch* cfg) {
+  if (!(cfg && cfg->ept)) L.ept = std::min(L.ept, max_ept<E>::value);
+}
+
 // Z = E element-wise (Sec. 3: assignment through the copy skeleton).
 template <class E, class T>
 int eval(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
@@ -335,9 +350,10 @@ int eval(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
   leaf_info li = info_of(e);
   li.addr_or |= reinterpret_cast<uintptr_t>(z);
   launch L = resolve(0, sizeof(T), rows, cols, cfg, li.aligned(16));
+  clamp_ept<E>(L, cfg);
   const int vec = L.vec_bytes / (int)sizeof(T);
   return with_vec<T>(vec, [&](auto Nc) {
-    return with_ept(L.ept, [&](auto Ec) {
+    return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_ew<E, T, N, EPT>), dim3(L.split), dim3(L.block), 0, st, e, z, n);
       return hip_check(hipGetLastError(), "k_ew launch");
@@ -363,12 +379,13 @@ int reduce_full(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launc
   const int64_t n = rows * cols;
   leaf_info li = info_of(e);
   launch L = resolve(FX_R_ACCU, sizeof(T), rows, cols, cfg, li.aligned(16));
+  clamp_ept<E>(L, cfg);
   const int vec = L.vec_bytes / (int)sizeof(T);
   ws_layout W = workspace_for(FX_R_ACCU, rows, cols, L, vec);
   if (L.split > 1 && (!ws || ws_bytes < W.total()))
     return fail(FX_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", W.total(), ws_bytes);
   return with_vec<T>(vec, [&](auto Nc) {
-    return with_ept(L.ept, [&](auto Ec) {
+    return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_full<E, M, D, N, EPT>), dim3(L.split), dim3(L.block), 0, st, e, n,
                          ws ? ws_partials<D>(ws, W) : nullptr, ws ? ws_counters(ws) : nullptr,
@@ -398,6 +415,7 @@ int reduce_dim(int kind, const E& e, O* out, void* ws, size_t ws_bytes, const fx
   leaf_info li = info_of(e);
   const int W16 = 16 / (int)sizeof(T);
   launch L = resolve(kind, sizeof(T), rows, cols, cfg, li.aligned(16) && rows % W16 == 0);
+  clamp_ept<E>(L, cfg);
   const int vec = L.vec_bytes / (int)sizeof(T);
   ws_layout W = workspace_for(kind, rows, cols, L, vec);
   if (W.total() > 0 && (!ws || ws_bytes < W.total()))
@@ -412,7 +430,7 @@ int reduce_dim(int kind, const E& e, O* out, void* ws, size_t ws_bytes, const fx
     }
     const int64_t rpc = ceil_div(ceil_div(rows, L.split), vec) * vec;
     return with_vec<T>(vec, [&](auto Nc) {
-      return with_ept(L.ept, [&](auto Ec) {
+      return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
         constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
         hipLaunchKernelGGL((k_colsum<E, O, N, EPT>), dim3((unsigned)cols, L.split), dim3(L.block), 0,
                            st, e, rows, L.split, rpc, parts, ctr, out);
@@ -423,7 +441,7 @@ int reduce_dim(int kind, const E& e, O* out, void* ws, size_t ws_bytes, const fx
   const int64_t cpc = ceil_div(cols, L.split);
   const int64_t rblocks = ceil_div(rows, (int64_t)L.block * vec);
   return with_vec<T>(vec, [&](auto Nc) {
-    return with_ept(L.ept, [&](auto Ec) {
+    return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_rowsum<E, O, N, EPT>), dim3((unsigned)rblocks, L.split), dim3(L.block), 0,
                          st, e, rows, cols, L.split, cpc, parts, ctr, out);

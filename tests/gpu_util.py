@@ -59,3 +59,31 @@ def assert_close(got, value, mu, dtype, what, out_dtype=None):
             what, rep, bad.tolist(), np.asarray(got).ravel()[bad].tolist(),
             np.asarray(value).ravel()[bad].tolist()))
     return rep
+
+
+def oracle_expr(nodes):
+    """The oracle's expression for generated tree nodes (children first)."""
+    built = []
+    for (op, a, b, inp, val) in nodes:
+        if op == "leaf":
+            e = oracle.leaf(inp)
+        elif op == "const":
+            e = oracle.const(val)
+        elif op == "neg":
+            e = -built[a]
+        elif op == "abs":
+            e = oracle.abs_(built[a])
+        elif op == "exp":
+            e = oracle.exp(built[a])
+        elif op == "sqrt":
+            e = oracle.sqrt(built[a])
+        else:
+            e = oracle.E(op, (built[a], built[b]))
+        built.append(e)
+    return built[-1]
+
+
+def tree_inputs(seed, expr, k, n, dtype):
+    from synth import trees
+    host = [synth.fill(seed, trees.input_tensor_id(expr, q), n, dtype) for q in range(k)]
+    return host, [to_dev(h, dtype) for h in host]

@@ -1,0 +1,114 @@
+"""GPU parity of run-time tapes (random trees) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import (assert_close, empty, from_dev, need_gpu, oracle_expr, to_dev,
+                      tree_inputs)
+from synth import trees
+
+pytestmark = pytest.mark.gpu
+
+FP = ["f32", "f64", "bf16", "f16"]
+ACC = {"f32": "f32", "bf16": "f32", "f16": "f32", "f64": "f64"}
+
+
+def _run(fx, torch, nodes, k, seed, e, dtype, shape, kind, cfg=None):
+    n = shape[0] * shape[1]
+    host, dev = tree_inputs(seed, e, k, n, dtype)
+    tape = fx.Tape(nodes)
+    dcode = {"f32": fx.F32, "f64": fx.F64, "bf16": fx.BF16, "f16": fx.F16}[dtype]
+    red = {0: None, fx.R_ACCU: "accu", fx.R_NORM: "norm", fx.R_COLSUM: "colsum",
+           fx.R_ROWSUM: "rowsum"}[kind]
+    if kind == 0:
+        out, od = empty(n, dtype), dtype
+    elif kind in (fx.R_ACCU, fx.R_NORM):
+        out, od = torch.zeros(1, dtype=torch.float64, device="cuda"), "f64"
+    else:
+        out, od = empty(shape[1] if kind == fx.R_COLSUM else shape[0], ACC[dtype]), ACC[dtype]
+    ws = fx.workspace(kind, dcode, shape, cfg) if kind else None
+    fx.fx_tape_eval(tape, dev, out, shape, kind, ws, cfg=cfg, dt=dcode)
+    torch.cuda.synchronize()
+    v, mu = oracle.evaluate(oracle_expr(nodes), host, dtype, shape=shape, reduce=red)
+    out_half = dtype if (kind == 0 and dtype in ("bf16", "f16")) else None
+    return assert_close(from_dev(out, od), v, mu, dtype,
+                        "tape seed %d tree %d %s kind %d %s" % (seed, e, dtype, kind, shape),
+                        out_dtype=out_half)
+
+
+@pytest.mark.parametrize("dtype", FP)
+@pytest.mark.parametrize("e", range(0, 48, 3))
+def test_random_trees_elementwise(dtype, e):
+    torch, fx = need_gpu()
+    nodes, k, _ = trees.random_tree(4, e)
+    _run(fx, torch, nodes, k, 4, e, dtype, (20000 + 7 * e, 1), 0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("e", range(1, 48, 4))
+def test_random_trees_accu_and_norm(dtype, e):
+    torch, fx = need_gpu()
+    nodes, k, _ = trees.random_tree(4, e)
+    _run(fx, torch, nodes, k, 4, e, dtype, (50000 + e, 1), fx.R_ACCU)
+    _run(fx, torch, nodes, k, 4, e, dtype, (250, 201), fx.R_NORM)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("e", range(2, 40, 5))
+def test_random_trees_dim_sums(dtype, e):
+    torch, fx = need_gpu()
+    nodes, k, _ = trees.random_tree(5, e, depth=(2, 8))
+    _run(fx, torch, nodes, k, 5, e, dtype, (1024, 77), fx.R_COLSUM)
+    _run(fx, torch, nodes, k, 5, e, dtype, (1000, 65), fx.R_ROWSUM)
+    _run(fx, torch, nodes, k, 5, e, dtype, (7, 300), fx.R_COLSUM)   # thin columns
+
+
+@pytest.mark.parametrize("cfg", [(64, 1, 4, 0), (128, 2, 16, 0), (256, 1, 16, 5),
+                                 (512, 2, 16, 0), (256, 1, 2, 0)])
+def test_tape_configs(cfg):
+    torch, fx = need_gpu()
+    nodes, k, _ = trees.random_tree(5, 11, depth=(6, 8))
+    for dtype in ("f32", "bf16"):
+        if cfg[2] == 2 and dtype == "f32":
+            continue
+        if cfg[2] == 4 and dtype == "bf16":
+            with pytest.raises(fx.FxError):
+                _run(fx, torch, nodes, k, 5, 11, dtype, (3 * 4096 + 5, 1), 0, cfg)
+            continue
+        _run(fx, torch, nodes, k, 5, 11, dtype, (3 * 4096 + 5, 1), 0, cfg)
+        _run(fx, torch, nodes, k, 5, 11, dtype, (3 * 4096 + 5, 1), fx.R_ACCU, cfg)
+
+
+def test_tape_ept_cap():
+    torch, fx = need_gpu()
+    nodes, k, _ = trees.random_tree(4, 3)
+    with pytest.raises(fx.FxError) as ei:
+        _run(fx, torch, nodes, k, 4, 3, "f32", (4096, 1), 0, (256, 4, 16, 0))
+    assert ei.value.code == 6
+
+
+def test_tape_matches_fused_c2():
+    """The C2 expression as a tape: same oracle rule, and close to the fused
+    kernel (they may differ only by contraction)."""
+    torch, fx = need_gpu()
+    X, Y, W = 0, 1, 2
+    nodes = [("leaf", -1, -1, X, 0), ("leaf", -1, -1, Y, 0), ("add", 0, 1, -1, 0),
+             ("leaf", -1, -1, W, 0), ("abs", 3, -1, -1, 0), ("neg", 4, -1, -1, 0),
+             ("exp", 5, -1, -1, 0), ("mul", 2, 6, -1, 0), ("const", -1, -1, -1, 1.0),
+             ("mul", 0, 0, -1, 0), ("add", 8, 9, -1, 0), ("div", 7, 10, -1, 0)]
+    shape = (1024, 300)
+    _run(fx, torch, nodes, 3, 2, 0, "f32", shape, 0)
+    _run(fx, torch, nodes, 3, 2, 0, "f64", shape, fx.R_COLSUM)
+
+
+def test_constant_tree():
+    torch, fx = need_gpu()
+    nodes = [("const", -1, -1, -1, 2.0), ("const", -1, -1, -1, 0.5), ("div", 0, 1, -1, 0)]
+    tape = fx.Tape(nodes)
+    out = empty(1000, "f32")
+    fx.fx_tape_eval(tape, [], out, (1000, 1), 0, dt=fx.F32)
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.fx_tape_eval(tape, [], s, (1000, 1), fx.R_ACCU, fx.workspace(fx.R_ACCU, fx.F32, (1000, 1)),
+                    dt=fx.F32)
+    torch.cuda.synchronize()
+    assert (out == 4.0).all().item() and s.item() == 4000.0

@@ -275,3 +275,13 @@ def test_bad_trees_are_rejected():
         oracle.evaluate(X ^ Y, [np.ones(4), np.ones(4)], "f64")
     with pytest.raises(AssertionError):      # a leaf without an input
         oracle.evaluate(X + Y, [np.ones(4)], "f64")
+
+
+def test_f16_overflow_reading():
+    v = np.array([65519.0, 65520.0, -70000.0, 1.0])
+    mu = np.zeros(4)
+    got = np.array([65504.0, np.inf, -np.inf, 1.0])
+    ok, _ = oracle.check(got, v, mu, "f16", out_dtype="f16")
+    assert ok.all()
+    ok, _ = oracle.check(np.array([65504.0, 65504.0, -65504.0, 1.0]), v, mu, "f16", out_dtype="f16")
+    assert list(ok) == [True, False, False, True]
