@@ -136,6 +136,76 @@ def copy_ceiling(fx, torch, stream, nbytes=1 << 31, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def event_ms(torch, stream, fn, reps):
+    """Mean HIP-event time of fn() over reps launches after two warm-ups."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def precision_detail(fx, torch, stream, reps):
+    """The C1 expressions at 2^28 elements: BF16 and FP16 storage against the
+    FP32 storage reference (Z = X%Y + 2W and accu(X%Y))."""
+    import synth
+    m = 1 << 28
+    out = {}
+    for dt in ("f32", "bf16", "f16"):
+        X, Y, W = [torch.from_numpy(synth.fill(3, t, m, dt)) for t in range(3)]
+        if dt == "bf16":
+            X, Y, W = [t.view(torch.int16).view(torch.bfloat16) for t in (X, Y, W)]
+        X, Y, W = X.cuda(), Y.cuda(), W.cuda()
+        Z = torch.empty_like(X)
+        s = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ws = fx.workspace(fx.R_ACCU, fx.dtype_code(X), (m, 1))
+        es = X.element_size()
+        zt = event_ms(torch, stream, lambda: fx.fx_c1_z(X, Y, W, Z, stream=stream), reps)
+        at = event_ms(torch, stream, lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), reps)
+        out[dt] = {"z_ms": round(zt, 4), "z_GB/s": round(4 * es * m / zt / 1e6, 1),
+                   "accu_ms": round(at, 4), "accu_GB/s": round(2 * es * m / at / 1e6, 1)}
+        del X, Y, W, Z
+        torch.cuda.empty_cache()
+    for dt in ("bf16", "f16"):
+        out[dt]["z_speedup_vs_f32_storage"] = round(out["f32"]["z_ms"] / out[dt]["z_ms"], 3)
+        out[dt]["accu_speedup_vs_f32_storage"] = round(out["f32"]["accu_ms"] / out[dt]["accu_ms"], 3)
+    return out
+
+
+def batch_detail(fx, torch, stream, reps):
+    """4096 random expressions (sizes 256..2^20, half ending in accu), FP32:
+    one persistent launch replayed from a HIP graph against 4096 separate
+    launches of the same tapes."""
+    import synth
+    from synth import trees
+    tset = trees.batch_set(4096)
+    items = []
+    for t in tset:
+        ins = [torch.from_numpy(synth.fill(4, trees.input_tensor_id(t["id"], q), t["n"], "f32")).cuda()
+               for q in range(t["n_inputs"])]
+        out = (torch.zeros(1, dtype=torch.float64, device="cuda") if t["reduce"] else
+               torch.empty(t["n"], dtype=torch.float32, device="cuda"))
+        items.append((fx.Tape(t["nodes"]), ins, out, t["n"], fx.R_ACCU if t["reduce"] else 0))
+    b = fx.Batch(items, fx.F32)
+    info = b.info()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = event_ms(torch, st, lambda: b.graph(st), reps)
+        one = event_ms(torch, st, lambda: b.launch(st), reps)
+        each = event_ms(torch, st, lambda: b.launch_each(st), max(3, reps // 5))
+    res = {"expressions": 4096, "tiles": info["n_tiles"], "tile_elems": info["tile_elems"],
+           "bytes": info["bytes"], "graph_ms": round(g, 4), "persistent_launch_ms": round(one, 4),
+           "separate_launches_ms": round(each, 4), "speedup_vs_separate": round(each / g, 2),
+           "graph_GB/s": round(info["bytes"] / g / 1e6, 1)}
+    b.destroy()
+    return res
+
+
 PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
                   for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp")]
@@ -221,7 +291,8 @@ def main():
            for r in RESULTS}
     detail = {"fp32_fused": per}
     dominant = max(RESULTS, key=lambda r: ms[r])
-    achieved = wl.bytes[dominant] / (ms[dominant] * 1e-3) / 1e9
+    dominant_bytes = wl.bytes[dominant]
+    achieved = dominant_bytes / (ms[dominant] * 1e-3) / 1e9
 
     if not a.no_extra:
         log("bench: unfused FP32 baseline")
@@ -243,6 +314,12 @@ def main():
         torch.cuda.empty_cache()
         log("bench: copy ceiling")
         detail["copy_ceiling_GB/s"] = round(copy_ceiling(fx, torch, stream), 1)
+        log("bench: precision workload, 2^28 elements")
+        detail["precision_2^28"] = precision_detail(fx, torch, stream, 20)
+        torch.cuda.empty_cache()
+        log("bench: batch of 4096 expressions")
+        detail["batch_4096"] = batch_detail(fx, torch, stream, 20)
+        torch.cuda.empty_cache()
 
     if a.profile:
         log("bench: 1 GiB reference copy")
@@ -274,7 +351,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic() if dominant == "z" else None,
-                     "algorithmic_bytes": wl.bytes[dominant]},
+                     "algorithmic_bytes": dominant_bytes},
         "cpu_baseline": cpu,
         "detail": detail,
     }

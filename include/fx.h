@@ -306,10 +306,75 @@ int fx_batch_launch(fx_batch* b, void* stream);
  * later calls: replay the graph on `stream` (one hipGraphLaunch). */
 int fx_batch_graph(fx_batch* b, void* stream);
 
+/* The same work as count separate launches, one fx_tape_eval per item with
+ * the library's default configuration (the comparison point of the
+ * persistent launch).  Reducing items use workspaces owned by the batch. */
+int fx_batch_launch_each(fx_batch* b, void* stream);
+
 int fx_batch_describe(const fx_batch* b, fx_batch_info* out);
 
 /* Frees the batch's device tables and graph (synchronises its last stream). */
 void fx_batch_destroy(fx_batch* b);
+
+/* ---- autotuning -----------------------------------------------------------
+ * The timing core of the exhaustive autotuner and the learned cost model
+ * that replaces it.  Neither appears in the paper; they choose the launch
+ * configuration (block, EPT, vector width, split) the kernels above take. */
+
+/* Time tape t, run exactly as fx_tape_eval(t, dt, inputs, n_inputs, shape,
+ * kind, out, ws, ...) would run it, under each of cfgs[0..n_cfgs): `warmup`
+ * untimed launches, then `reps` launches each bracketed by HIP events on
+ * `stream`.  ms[c*reps + r] receives the times in milliseconds; a
+ * configuration that is not compiled or does not fit (FX_E_UNSUPPORTED,
+ * FX_E_CONFIG, FX_E_WORKSPACE) gets NaN and the sweep goes on.  ws must hold
+ * the largest workspace among the configurations.  Synchronous. */
+int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                 fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
+                 const fx_launch* cfgs, int32_t n_cfgs, int32_t warmup, int32_t reps,
+                 float* ms, void* stream);
+
+/* The learned cost model: a two-layer perceptron (standardised features ->
+ * hidden ReLU layer -> one softmax head per launch knob), trained on the
+ * autotuner's best configurations with softmax cross-entropy and Adam, by
+ * hand-written FP32 kernels (no matrix cores).  Parameters: one flat FP32
+ * array W1 [hidden x F] row-major, b1 [hidden], W2 [C x hidden], b2 [C],
+ * C = sum of head sizes. */
+typedef struct fx_model fx_model;
+
+/* F <= 64 features, hidden <= 256, up to 8 heads of >= 2 classes each
+ * (C <= 64).  Parameters start at zero: set them with fx_model_set. */
+int fx_model_create(int32_t n_features, int32_t hidden, const int32_t* head_sizes,
+                    int32_t n_heads, fx_model** out);
+int32_t fx_model_num_params(const fx_model* m);
+
+/* Host arrays (any may be NULL to keep the current values): parameters,
+ * feature means and standard deviations (> 0).  New parameters reset Adam. */
+int fx_model_set(fx_model* m, const float* params, const float* mean, const float* stdv);
+/* Copy parameters / standardisation to host arrays (synchronous). */
+int fx_model_get(fx_model* m, float* params, float* mean, float* stdv);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on a device batch: X [batch x F]
+ * row-major FP32, labels [batch x n_heads] int32 class indices.  *d_loss
+ * (device, may be NULL) gets the mean cross-entropy before the update.
+ * Gradients are summed over the batch in row order (deterministic). */
+int fx_model_train_step(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
+                        float lr, float* d_loss, void* stream);
+
+/* The gradient of the mean cross-entropy (no update) into d_grad [params]. */
+int fx_model_grad(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
+                  float* d_grad, float* d_loss, void* stream);
+
+/* Inference on a device batch: logits [batch x C] and/or per-head argmax
+ * [batch x n_heads] (either may be NULL, not both). */
+int fx_model_forward(const fx_model* m, const float* d_X, int32_t batch, float* d_logits,
+                     int32_t* d_choice, void* stream);
+
+/* Host twin of the inference kernel for one feature row (no GPU): the same
+ * FP32 fused multiply-add arithmetic in the same order.  Uses the parameters
+ * as of the last fx_model_set / fx_model_get. */
+int fx_model_choose(const fx_model* m, const float* features, int32_t* choice);
+
+void fx_model_destroy(fx_model* m);
 
 /* ---- measurement kernels ------------------------------------------------- */
 

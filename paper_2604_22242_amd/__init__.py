@@ -116,8 +116,22 @@ _SIGS = {
                              ctypes.POINTER(_P)]),
     "fx_batch_launch": (_I, [_P, _P]),
     "fx_batch_graph": (_I, [_P, _P]),
+    "fx_batch_launch_each": (_I, [_P, _P]),
     "fx_batch_describe": (_I, [_P, ctypes.POINTER(BatchInfo)]),
     "fx_batch_destroy": (None, [_P]),
+    "fx_tune_time": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
+                          _LP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_float), _P]),
+    "fx_model_create": (_I, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                             ctypes.c_int32, ctypes.POINTER(_P)]),
+    "fx_model_num_params": (ctypes.c_int32, [_P]),
+    "fx_model_set": (_I, [_P, _P, _P, _P]),
+    "fx_model_get": (_I, [_P, _P, _P, _P]),
+    "fx_model_train_step": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P]),
+    "fx_model_grad": (_I, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "fx_model_forward": (_I, [_P, _P, ctypes.c_int32, _P, _P, _P]),
+    "fx_model_choose": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]),
+    "fx_model_destroy": (None, [_P]),
     "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
     "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
     "fx_bw_write": (_I, [_P, _SZ, ctypes.c_uint32, _LP, _P]),
@@ -130,6 +144,13 @@ def lib():
     """The loaded libfx.so.  Raises if it has not been built."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime; loading it first lets libfx.so bind
+        # to that same runtime (one runtime per process) instead of a second
+        # copy from /opt/rocm.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise FxError(-1, "%s is missing: run paper_2604_22242_amd.build first" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
@@ -426,6 +447,9 @@ class Batch:
     def graph(self, stream=None):
         return check(lib().fx_batch_graph(self.handle, _stream(stream)))
 
+    def launch_each(self, stream=None):
+        return check(lib().fx_batch_launch_each(self.handle, _stream(stream)))
+
     def info(self) -> dict:
         inf = BatchInfo()
         check(lib().fx_batch_describe(self.handle, ctypes.byref(inf)))
@@ -452,12 +476,132 @@ def fx_batch_graph(batch: Batch, stream=None):
     return batch.graph(stream)
 
 
+def fx_batch_launch_each(batch: Batch, stream=None):
+    return batch.launch_each(stream)
+
+
 def fx_batch_describe(batch: Batch) -> dict:
     return batch.info()
 
 
 def fx_batch_destroy(batch: Batch):
     batch.destroy()
+
+
+# ---- autotuning ---------------------------------------------------------------------------
+
+
+def fx_tune_time(tape: Tape, inputs, out, shape, kind, cfgs, ws=None, warmup=2, reps=5,
+                 stream=None, dt=None):
+    """Times (ms) of `tape` under each configuration: a len(cfgs) x reps list."""
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    if dt is None:
+        dt = dtype_code(inputs[0]) if inputs else dtype_code(out)
+    carr = (Launch * max(1, len(cfgs)))(*[Launch(*c) for c in cfgs])
+    ms = (ctypes.c_float * (max(1, len(cfgs)) * reps))()
+    p, nb = _ws(ws)
+    check(lib().fx_tune_time(tape.handle, dt, arr, len(inputs), _shape(shape), kind, _ptr(out),
+                             p, nb, carr, len(cfgs), warmup, reps, ms, _stream(stream)))
+    return [[ms[c * reps + r] for r in range(reps)] for c in range(len(cfgs))]
+
+
+# ---- learned cost model -------------------------------------------------------------------
+
+
+class Model:
+    """An fx_model handle (a two-layer perceptron with one softmax head per
+    launch knob)."""
+
+    def __init__(self, n_features, hidden, heads):
+        self.n_features, self.hidden, self.heads = n_features, hidden, tuple(heads)
+        hs = (ctypes.c_int32 * len(heads))(*heads)
+        self.handle = ctypes.c_void_p()
+        check(lib().fx_model_create(n_features, hidden, hs, len(heads),
+                                    ctypes.byref(self.handle)))
+
+    @property
+    def n_params(self):
+        return lib().fx_model_num_params(self.handle)
+
+    def set(self, params=None, mean=None, std=None):
+        import numpy as np
+        def p(a):
+            return None if a is None else np.ascontiguousarray(a, np.float32)
+        params, mean, std = p(params), p(mean), p(std)
+        self._hold = (params, mean, std)
+        check(lib().fx_model_set(self.handle, *[None if a is None else a.ctypes.data
+                                                for a in (params, mean, std)]))
+
+    def get(self):
+        import numpy as np
+        params = np.empty(self.n_params, np.float32)
+        mean = np.empty(self.n_features, np.float32)
+        std = np.empty(self.n_features, np.float32)
+        check(lib().fx_model_get(self.handle, params.ctypes.data, mean.ctypes.data,
+                                 std.ctypes.data))
+        return params, mean, std
+
+    def train_step(self, X, labels, lr, loss=None, stream=None):
+        return check(lib().fx_model_train_step(self.handle, _ptr(X), _ptr(labels), X.shape[0],
+                                               float(lr), _ptr(loss), _stream(stream)))
+
+    def grad(self, X, labels, grad, loss=None, stream=None):
+        return check(lib().fx_model_grad(self.handle, _ptr(X), _ptr(labels), X.shape[0],
+                                         _ptr(grad), _ptr(loss), _stream(stream)))
+
+    def forward(self, X, logits=None, choice=None, stream=None):
+        return check(lib().fx_model_forward(self.handle, _ptr(X), X.shape[0], _ptr(logits),
+                                            _ptr(choice), _stream(stream)))
+
+    def choose(self, features):
+        x = (ctypes.c_float * self.n_features)(*[float(v) for v in features])
+        out = (ctypes.c_int32 * len(self.heads))()
+        check(lib().fx_model_choose(self.handle, x, out))
+        return list(out)
+
+    def destroy(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fx_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def fx_model_create(n_features, hidden, heads) -> Model:
+    return Model(n_features, hidden, heads)
+
+
+def fx_model_num_params(m: Model) -> int:
+    return m.n_params
+
+
+def fx_model_set(m: Model, params=None, mean=None, std=None):
+    return m.set(params, mean, std)
+
+
+def fx_model_get(m: Model):
+    return m.get()
+
+
+def fx_model_train_step(m: Model, X, labels, lr, loss=None, stream=None):
+    return m.train_step(X, labels, lr, loss, stream)
+
+
+def fx_model_grad(m: Model, X, labels, grad, loss=None, stream=None):
+    return m.grad(X, labels, grad, loss, stream)
+
+
+def fx_model_forward(m: Model, X, logits=None, choice=None, stream=None):
+    return m.forward(X, logits, choice, stream)
+
+
+def fx_model_choose(m: Model, features):
+    return m.choose(features)
+
+
+def fx_model_destroy(m: Model):
+    m.destroy()
 
 
 # ---- measurement kernels ------------------------------------------------------------

@@ -112,6 +112,10 @@ using namespace fx;
 struct fx_batch {
   fx_dtype dt;
   fx_batch_info info;
+  std::vector<fx_batch_item> items;  // for separate launches
+  std::vector<tape_prog> progs;
+  std::vector<size_t> ws_off;        // workspace offset per reducing item
+  void* d_ws = nullptr;
   batch_desc* d_descs = nullptr;
   tape_prog* d_progs = nullptr;
   uint32_t* d_tiles = nullptr;
@@ -131,6 +135,7 @@ static void batch_free(fx_batch* b) {
   hipFree(b->d_tiles);
   hipFree(b->d_partials);
   hipFree(b->d_counters);
+  hipFree(b->d_ws);
 }
 
 static int elem_of(fx_dtype dt) {
@@ -236,6 +241,16 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   const int64_t grid_default = (int64_t)device_cus() * 8;
   I.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(c.split ? c.split : grid_default,
                                                           std::max<int64_t>(1, I.n_tiles)));
+  // workspaces for launching the items one by one (default configuration)
+  b->items.assign(items, items + count);
+  b->progs = progs;
+  b->ws_off.assign(count, 0);
+  size_t ws_total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (items[i].kind != FX_R_ACCU) continue;
+    b->ws_off[i] = ws_total;
+    ws_total += (fx_workspace_bytes(FX_R_ACCU, dt, fx_shape{items[i].n, 1}, nullptr) + 255) & ~(size_t)255;
+  }
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
     if (e == hipSuccess && bytes) e = hipMalloc(p, bytes);
@@ -251,7 +266,9 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     e = hipMemcpy(b->d_progs, progs.data(), sizeof(tape_prog) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess && I.n_tiles)
     e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint32_t) * I.n_tiles, hipMemcpyHostToDevice);
+  alloc(&b->d_ws, std::max<size_t>(256, ws_total));
   if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(unsigned) * std::max(1, count));
+  if (e == hipSuccess) e = hipMemset(b->d_ws, 0, std::max<size_t>(256, ws_total));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     int rc = hip_check(e, "fx_batch_create");
@@ -302,6 +319,27 @@ int fx_batch_graph(fx_batch* b, void* stream) {
     b->exec = x;
   }
   return hip_check(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
+}
+
+int fx_batch_launch_each(fx_batch* b, void* stream) {
+  if (!b) return fail(FX_E_ARG, "NULL batch");
+  b->last_stream = S(stream);
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const fx_batch_item& it = b->items[i];
+    const fx_shape sh{it.n, 1};
+    void* ws = it.kind == FX_R_ACCU ? static_cast<char*>(b->d_ws) + b->ws_off[i] : nullptr;
+    const size_t wsb = it.kind == FX_R_ACCU ? fx_workspace_bytes(FX_R_ACCU, b->dt, sh, nullptr) : 0;
+    int rc = FX_OK;
+    switch (b->dt) {
+      case FX_F32: rc = tape_eval_typed<float>(b->progs[i], it.inputs, sh, it.kind, it.out, ws, wsb, nullptr, S(stream)); break;
+      case FX_F64: rc = tape_eval_typed<double>(b->progs[i], it.inputs, sh, it.kind, it.out, ws, wsb, nullptr, S(stream)); break;
+      case FX_BF16: rc = tape_eval_typed<bf16_t>(b->progs[i], it.inputs, sh, it.kind, it.out, ws, wsb, nullptr, S(stream)); break;
+      case FX_F16: rc = tape_eval_typed<f16_t>(b->progs[i], it.inputs, sh, it.kind, it.out, ws, wsb, nullptr, S(stream)); break;
+      default: rc = fail(FX_E_DTYPE, "bad dtype");
+    }
+    if (rc != FX_OK) return rc;
+  }
+  return FX_OK;
 }
 
 int fx_batch_describe(const fx_batch* b, fx_batch_info* out) {

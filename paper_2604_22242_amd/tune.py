@@ -1,0 +1,206 @@
+"""Exhaustive autotuner of launch configurations, and the features the
+learned cost model reads.
+
+The timing itself is native (fx_tune_time: HIP events around each launch on
+the stream); this module chooses the configuration grid, runs the search
+(exhaustive, or successive halving for cheap training labels), and keeps an
+append-only JSONL timing database that a re-run resumes (keys already
+present are skipped).
+
+    python -m paper_2604_22242_amd.tune --set train --start 0 --count 1000 \
+        --db tune_train.jsonl --mode halving
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+from . import (BF16, F32, R_ACCU, R_COLSUM, R_NORM, R_ROWSUM, Tape, fx_tune_time,
+               fx_workspace_bytes, lib)
+
+BLOCKS = (64, 128, 256, 512)
+EPTS = (1, 2)
+VECS = ("elem", 16)
+KIND = {None: 0, "accu": R_ACCU, "colsum": R_COLSUM, "rowsum": R_ROWSUM, "norm": R_NORM}
+DTYPE = {"f32": F32, "bf16": BF16}
+ELEM = {"f32": 4, "bf16": 2}
+
+
+def split_choices(reduce, cus=256):
+    """Four values of the `split` knob per reduction kind (0 = library
+    default: one tile per block for element-wise, the heuristics otherwise)."""
+    if reduce is None:
+        return (0, 2 * cus, 8 * cus, 32 * cus)
+    if reduce in ("accu", "norm"):
+        return (cus, 2 * cus, 4 * cus, 8 * cus)
+    if reduce == "colsum":
+        return (0, 1, 4, 16)
+    return (0, 16, 64, 256)
+
+
+DEFAULT = (0, 0, 0, 0)  # the library's own choice (timed for comparison, never a label)
+
+
+def grid(reduce, dtype, cus=256):
+    """All configurations: list of ((block, ept, vec_bytes, split), labels)
+    where labels are the class index of each knob; the last entry is the
+    library default with labels None."""
+    out = []
+    for bi, b in enumerate(BLOCKS):
+        for ei, e in enumerate(EPTS):
+            for vi, v in enumerate(VECS):
+                vb = ELEM[dtype] if v == "elem" else v
+                for si, s in enumerate(split_choices(reduce, cus)):
+                    out.append(((b, e, vb, s), (bi, ei, vi, si)))
+    out.append((DEFAULT, None))
+    return out
+
+
+HEADS = (len(BLOCKS), len(EPTS), len(VECS), 4)
+FEATURES = ["add", "sub", "mul", "div", "neg", "abs", "exp", "sqrt", "consts", "depth",
+            "instructions", "slots", "inputs", "bf16", "log2_n", "log2_rows", "log2_cols",
+            "red_none", "red_accu", "red_colsum", "red_rowsum", "red_norm", "bytes_per_elem",
+            "transcendental", "log2_bytes"]
+
+
+def features(info: dict, dtype: str, shape, reduce) -> list:
+    """The model's input vector for one (tree, size, dtype, reduction)."""
+    oc = info["op_count"]
+    rows, cols = shape
+    n = max(1, rows * cols)
+    bpe = ELEM[dtype] * (info["n_inputs"] + (1 if reduce is None else 0))
+    red = [1.0 if reduce == r else 0.0 for r in (None, "accu", "colsum", "rowsum", "norm")]
+    return [float(c) for c in oc] + [
+        float(info["n_consts"]), float(info["depth"]), float(info["n_instructions"]),
+        float(info["n_slots"]), float(info["n_inputs"]), 1.0 if dtype == "bf16" else 0.0,
+        math.log2(n), math.log2(max(1, rows)), math.log2(max(1, cols))] + red + [
+        float(bpe), float(oc[3] + oc[6] + oc[7]), math.log2(max(1, bpe * n))]
+
+
+def key_of(item) -> str:
+    h = hashlib.sha1(json.dumps(item["nodes"]).encode()).hexdigest()[:16]
+    return "%s:%dx%d:%s:%s" % (h, item["shape"][0], item["shape"][1], item["dtype"], item["reduce"])
+
+
+class Pool:
+    """Input, output and workspace buffers reused by every timed item (the
+    values are seeded U[-1,1]; timing does not depend on them)."""
+
+    def __init__(self, max_n=(1 << 28) + (1 << 16), dtypes=("f32", "bf16")):
+        import torch
+        import synth
+        self.torch = torch
+        self.max_n = max_n
+        self.inputs, self.out = {}, None
+        for dt in dtypes:
+            bufs = []
+            for q in range(4):
+                h = synth.fill(5, 100 + q, max_n, dt)
+                t = torch.from_numpy(h)
+                if dt == "bf16":
+                    t = t.view(torch.int16).view(torch.bfloat16)
+                bufs.append(t.cuda())
+                del h
+            self.inputs[dt] = bufs
+        self.out = torch.empty(max_n * 4 + 4096, dtype=torch.uint8, device="cuda")
+        self.ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+
+    def views(self, dt, n, k):
+        return [b[:n] for b in self.inputs[dt][:k]]
+
+
+def tune_item(item, pool, mode="exhaustive", warmup=2, reps=5, cus=256):
+    """Time every configuration of the grid for one item.  Returns a record
+    for the timing database."""
+    tape = Tape(item["nodes"])
+    info = tape.info()
+    dt, red, shape = item["dtype"], item["reduce"], item["shape"]
+    n = shape[0] * shape[1]
+    kind = KIND[red]
+    cfgs = grid(red, dt, cus)
+    ins = pool.views(dt, n, item["n_inputs"])
+    ws_need = max(fx_workspace_bytes(kind, DTYPE[dt], shape, c) for c, _ in cfgs) if kind else 0
+    assert ws_need <= pool.ws.numel(), "workspace pool too small"
+    ws = pool.ws if kind else None
+
+    def timed(idx, r):
+        t = fx_tune_time(tape, ins, pool.out, shape, kind, [cfgs[i][0] for i in idx], ws=ws,
+                         warmup=warmup, reps=r, dt=DTYPE[dt])
+        return {i: (statistics.median(v) if not any(math.isnan(x) for x in v) else float("nan"))
+                for i, v in zip(idx, t)}
+
+    t0 = time.perf_counter()
+    if mode == "exhaustive":
+        med = timed(list(range(len(cfgs))), reps)
+    else:  # successive halving: 1 rep for all, 3 for the best quarter, 5 for the best 4
+        med = timed(list(range(len(cfgs))), 1)
+        alive = sorted((i for i in med if not math.isnan(med[i])), key=lambda i: med[i])
+        alive = alive[:max(4, len(alive) // 4)]
+        med.update(timed(alive, 3))
+        alive = sorted(alive, key=lambda i: med[i])[:4]
+        med.update(timed(alive, reps))
+    if len(cfgs) - 1 not in med:  # the default is always timed fully
+        med.update(timed([len(cfgs) - 1], reps))
+    ok = [i for i in med if not math.isnan(med[i]) and cfgs[i][1] is not None]
+    best = min(ok, key=lambda i: med[i])
+    return {"key": key_of(item), "id": item["id"], "seed": item["seed"], "dtype": dt,
+            "reduce": red, "shape": list(shape), "info": info,
+            "features": features(info, dt, shape, red),
+            "configs": [list(c) for c, _ in cfgs],
+            "labels": [list(l) if l is not None else None for _, l in cfgs],
+            "ms": [med.get(i, float("nan")) for i in range(len(cfgs))],
+            "best": best, "best_ms": med[best], "default_ms": med[len(cfgs) - 1], "mode": mode,
+            "tune_seconds": time.perf_counter() - t0}
+
+
+def load_db(path):
+    recs = {}
+    if os.path.exists(path):
+        for line in open(path):
+            line = line.strip()
+            if line:
+                r = json.loads(line)
+                recs[r["key"]] = r
+    return recs
+
+
+def main(argv=None):
+    from synth import trees
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--set", choices=("train", "heldout"), default="train")
+    ap.add_argument("--start", type=int, default=0)
+    ap.add_argument("--count", type=int, default=100)
+    ap.add_argument("--db", required=True)
+    ap.add_argument("--mode", choices=("exhaustive", "halving"), default=None)
+    ap.add_argument("--max-n", type=int, default=(1 << 28) + (1 << 16))
+    a = ap.parse_args(argv)
+    seed = 5 if a.set == "train" else 6
+    mode = a.mode or ("halving" if a.set == "train" else "exhaustive")
+    lib()
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    done = load_db(a.db)
+    pool = Pool(a.max_n)
+    t0 = time.time()
+    with open(a.db, "a") as f:
+        for i in range(a.start, a.start + a.count):
+            item = trees.tuning_item(seed, i)
+            if item["n"] > a.max_n or key_of(item) in done:
+                continue
+            rec = tune_item(item, pool, mode, cus=cus)
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            if (i - a.start) % 100 == 0:
+                print("tune %s %d/%d  %.0fs" % (a.set, i - a.start, a.count, time.time() - t0),
+                      flush=True)
+    print("tune done %d items in %.0fs" % (a.count, time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

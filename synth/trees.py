@@ -165,3 +165,34 @@ def summary(trees) -> dict:
     return {"count": len(trees), "n_min": int(sizes.min()), "n_median": float(np.median(sizes)),
             "n_mean": float(sizes.mean()), "n_max": int(sizes.max()),
             "nodes_max": max(len(t["nodes"]) for t in trees)}
+
+
+REDUCTIONS = (None, "accu", "colsum", "rowsum", "norm")
+REDUCTION_P = (0.40, 0.15, 0.15, 0.15, 0.15)
+TUNE_STREAM = 3 * TREE_STREAM
+
+
+def tuning_item(seed: int, index: int) -> dict:
+    """One launch-configuration workload item: a tree of depth 2..8 over 1..4
+    inputs; n = round(2^U(12, 28)) rounded up to a multiple of 64; storage
+    FP32 or BF16; reduction none / accu / colsum / rowsum / norm with
+    probabilities .40/.15/.15/.15/.15; dimension sums view the data as
+    n_rows = 2^ceil(log2(n)/2) rows by ceil(n / n_rows) columns."""
+    nodes, k, D = random_tree(seed, index, depth=(2, 8))
+    r = Draws(seed, TUNE_STREAM + index)
+    n = int(round(2.0 ** (12 + 16 * r.uniform())))
+    n = (n + 63) // 64 * 64
+    dtype = "f32" if r.uniform() < 0.5 else "bf16"
+    u, acc, red = r.uniform(), 0.0, None
+    for cand, p in zip(REDUCTIONS, REDUCTION_P):
+        acc += p
+        if u < acc:
+            red = cand
+            break
+    if red in ("colsum", "rowsum"):
+        rows = 2 ** math.ceil(math.log2(n) / 2)
+        shape = (rows, -(-n // rows))
+    else:
+        shape = (n, 1)
+    return {"id": index, "seed": seed, "nodes": nodes, "n_inputs": k, "target_depth": D,
+            "n": shape[0] * shape[1], "shape": shape, "dtype": dtype, "reduce": red}

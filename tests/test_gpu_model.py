@@ -1,0 +1,166 @@
+"""GPU tests of the learned cost model's hand-written kernels against CPU
+references that share nothing with them: numpy float64 forward, torch CPU
+autograd gradients, central finite differences, a numpy Adam step."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+F, H, HEADS = 25, 64, (4, 2, 2, 4)
+C = sum(HEADS)
+
+
+def _params(rng):
+    W1 = rng.uniform(-1, 1, (H, F)) / np.sqrt(F)
+    b1 = rng.uniform(-0.1, 0.1, H)
+    W2 = rng.uniform(-1, 1, (C, H)) / np.sqrt(H)
+    b2 = rng.uniform(-0.1, 0.1, C)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)
+
+
+def _unpack(p):
+    p = p.astype(np.float64)
+    o = 0
+    W1 = p[o:o + H * F].reshape(H, F); o += H * F
+    b1 = p[o:o + H]; o += H
+    W2 = p[o:o + C * H].reshape(C, H); o += C * H
+    b2 = p[o:o + C]
+    return W1, b1, W2, b2
+
+
+def _forward64(p, X, mean, std):
+    W1, b1, W2, b2 = _unpack(p)
+    xn = (X.astype(np.float64) - mean) / std
+    h = np.maximum(xn @ W1.T + b1, 0)
+    return h @ W2.T + b2
+
+
+def _loss64(p, X, y, mean, std):
+    logits = _forward64(p, X, mean, std)
+    L, o = 0.0, 0
+    for q, k in enumerate(HEADS):
+        z = logits[:, o:o + k]
+        m = z.max(axis=1, keepdims=True)
+        lse = (m[:, 0] + np.log(np.exp(z - m).sum(axis=1)))
+        L += np.mean(lse - z[np.arange(len(y)), y[:, q]])
+        o += k
+    return L
+
+
+def _data(rng, B):
+    X = rng.normal(size=(B, F)).astype(np.float32) * 3 + 1
+    y = np.stack([rng.integers(0, k, B) for k in HEADS], axis=1).astype(np.int32)
+    return X, y
+
+
+def _model(fx, rng):
+    m = fx.Model(F, H, HEADS)
+    p = _params(rng)
+    mean = rng.normal(size=F).astype(np.float32)
+    std = rng.uniform(0.5, 2, F).astype(np.float32)
+    m.set(p, mean, std)
+    return m, p, mean, std
+
+
+def test_forward_and_choose():
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(1)
+    m, p, mean, std = _model(fx, rng)
+    X, _ = _data(rng, 513)
+    Xd = torch.from_numpy(X).cuda()
+    logits = torch.empty(513, C, device="cuda")
+    choice = torch.empty(513, len(HEADS), dtype=torch.int32, device="cuda")
+    m.forward(Xd, logits, choice)
+    torch.cuda.synchronize()
+    ref = _forward64(p, X, mean.astype(np.float64), std.astype(np.float64))
+    got = logits.cpu().numpy()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)) < 1e-4
+    ch = choice.cpu().numpy()
+    o = 0
+    for q, k in enumerate(HEADS):
+        assert np.array_equal(ch[:, q], np.argmax(got[:, o:o + k], axis=1))
+        o += k
+    for b in range(0, 513, 37):                 # the host twin decides identically
+        assert m.choose(X[b]) == list(ch[b])
+
+
+def test_gradient_matches_autograd_and_differences():
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(2)
+    m, p, mean, std = _model(fx, rng)
+    X, y = _data(rng, 300)
+    grad = torch.empty(m.n_params, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    m.grad(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), grad, loss)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    # CPU autograd in float64
+    pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    o = 0
+    W1 = pt[o:o + H * F].view(H, F); o += H * F
+    b1 = pt[o:o + H]; o += H
+    W2 = pt[o:o + C * H].view(C, H); o += C * H
+    b2 = pt[o:o + C]
+    xn = (torch.tensor(X, dtype=torch.float64) - torch.tensor(mean, dtype=torch.float64)) / \
+        torch.tensor(std, dtype=torch.float64)
+    logits = torch.relu(xn @ W1.T + b1) @ W2.T + b2
+    L, o = 0.0, 0
+    yt = torch.tensor(y, dtype=torch.int64)
+    for q, k in enumerate(HEADS):
+        L = L + torch.nn.functional.cross_entropy(logits[:, o:o + k], yt[:, q])
+        o += k
+    L.backward()
+    ref = pt.grad.numpy()
+    assert abs(loss.item() - L.item()) < 1e-5 * max(1, abs(L.item()))
+    assert np.max(np.abs(g - ref)) < 1e-5 * max(1.0, np.max(np.abs(ref)))
+    # central differences on a few parameters of each block
+    m64, s64 = mean.astype(np.float64), std.astype(np.float64)
+    for i in [0, 7, H * F - 1, H * F + 3, H * F + H + 11, m.n_params - 1]:
+        e = np.zeros(m.n_params)
+        e[i] = 1e-4
+        fd = (_loss64(p + e, X, y, m64, s64) - _loss64(p - e, X, y, m64, s64)) / 2e-4
+        assert abs(fd - g[i]) < 1e-4 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_adam_step_matches_numpy():
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(3)
+    m, p, mean, std = _model(fx, rng)
+    X, y = _data(rng, 128)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    grad = torch.empty(m.n_params, device="cuda")
+    m.grad(Xd, yd, grad)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    lr = 1e-2
+    m.train_step(Xd, yd, lr)
+    new = m.get()[0].astype(np.float64)
+    mom, v = 0.1 * g, 0.001 * g * g                 # first step from zero moments
+    want = p - lr * (mom / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+    assert np.max(np.abs(new - want)) < 1e-5
+
+
+def test_training_reduces_loss_on_separable_data():
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(4)
+    m = fx.Model(F, H, HEADS)
+    m.set(_params(rng), np.zeros(F, np.float32), np.ones(F, np.float32))
+    B = 1024
+    X = rng.normal(size=(B, F)).astype(np.float32)
+    y = np.stack([(X[:, 0] > 0) * 2 + (X[:, 1] > 0), X[:, 2] > 0, X[:, 3] + X[:, 4] > 0,
+                  np.digitize(X[:, 5], [-0.7, 0, 0.7])], axis=1).astype(np.int32)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    loss = torch.empty(1, device="cuda")
+    m.train_step(Xd, yd, 3e-3, loss)
+    torch.cuda.synchronize()
+    first = loss.item()
+    for _ in range(400):
+        m.train_step(Xd, yd, 3e-3, loss)
+    torch.cuda.synchronize()
+    assert loss.item() < 0.15 * first, (first, loss.item())
+    choice = torch.empty(B, 4, dtype=torch.int32, device="cuda")
+    m.forward(Xd, None, choice)
+    torch.cuda.synchronize()
+    assert (choice.cpu().numpy() == y).all(axis=1).mean() > 0.9

@@ -1,0 +1,40 @@
+"""CPU tests of the autotuner's configuration grid and model features."""
+import math
+
+from synth import trees
+
+
+def test_grid_shape_and_labels():
+    from paper_2604_22242_amd import tune
+    for red in (None, "accu", "colsum", "rowsum", "norm"):
+        for dt in ("f32", "bf16"):
+            g = tune.grid(red, dt)
+            assert len(g) == 4 * 2 * 2 * 4 + 1 and g[-1] == (tune.DEFAULT, None)
+            g = g[:-1]
+            assert len({c for c, _ in g}) == len(g)
+            for (b, e, v, s), (bi, ei, vi, si) in g:
+                assert tune.BLOCKS[bi] == b and tune.EPTS[ei] == e
+                assert v == (tune.ELEM[dt] if tune.VECS[vi] == "elem" else 16)
+                assert tune.split_choices(red)[si] == s
+
+
+def test_features():
+    from paper_2604_22242_amd import tune
+    info = {"op_count": [1, 0, 2, 1, 0, 1, 1, 0], "n_consts": 2, "depth": 4,
+            "n_instructions": 6, "n_slots": 5, "n_inputs": 3}
+    f = tune.features(info, "bf16", (4096, 2), "colsum")
+    assert len(f) == len(tune.FEATURES)
+    d = dict(zip(tune.FEATURES, f))
+    assert d["log2_n"] == 13 and d["log2_rows"] == 12 and d["log2_cols"] == 1
+    assert d["red_colsum"] == 1 and d["red_none"] == 0 and d["bf16"] == 1
+    assert d["bytes_per_elem"] == 6 and d["transcendental"] == 2
+    assert math.isclose(d["log2_bytes"], math.log2(6 * 8192))
+
+
+def test_tuning_items():
+    items = [trees.tuning_item(5, i) for i in range(400)]
+    assert all(4096 <= it["n"] <= (1 << 28) + (1 << 15) for it in items)
+    assert all(it["shape"][0] * it["shape"][1] == it["n"] for it in items)
+    assert {it["dtype"] for it in items} == {"f32", "bf16"}
+    assert trees.tuning_item(5, 7) == trees.tuning_item(5, 7)
+    assert trees.tuning_item(6, 7) != trees.tuning_item(5, 7)
