@@ -24,14 +24,14 @@ import time
 import numpy as np
 
 from . import Model, lib
-from .tune import BLOCKS, EPTS, FEATURES, HEADS, VECS, load_db, split_choices
+from .tune import BLOCKS, EPTS, FEATURES, HEADS, VECS, load_db, record_grid, split_choices
 
 HIDDEN = 64
 
 
 def dataset(records):
     X = np.array([r["features"] for r in records], np.float32)
-    Y = np.array([r["labels"][r["best"]] for r in records], np.int32)
+    Y = np.array([record_grid(r)[r["best"]][1] for r in records], np.int32)
     return X, Y
 
 
@@ -106,12 +106,10 @@ def evaluate(m: Model, records, cus=256):
         t0 = time.perf_counter()
         ch = m.choose(r["features"])
         lat.append(time.perf_counter() - t0)
-        cfg = list(config_of(ch, r["reduce"], r["dtype"], cus))
-        try:
-            t = r["ms"][r["configs"].index(cfg)]
-        except ValueError:
-            t = float("nan")
-        if not (t == t):
+        cfg = config_of(ch, r["reduce"], r["dtype"], r.get("cus", cus))
+        cfgs = [c for c, _ in record_grid(r)]
+        t = r["ms"][cfgs.index(cfg)] if cfg in cfgs else None
+        if t is None or not (t == t):
             missing += 1
             t = r["default_ms"]
         ratios.append(t / r["best_ms"])

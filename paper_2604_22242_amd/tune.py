@@ -149,14 +149,18 @@ def tune_item(item, pool, mode="exhaustive", warmup=2, reps=5, cus=256):
         med.update(timed([len(cfgs) - 1], reps))
     ok = [i for i in med if not math.isnan(med[i]) and cfgs[i][1] is not None]
     best = min(ok, key=lambda i: med[i])
+    r4 = lambda v: float("%.4g" % v)
     return {"key": key_of(item), "id": item["id"], "seed": item["seed"], "dtype": dt,
-            "reduce": red, "shape": list(shape), "info": info,
-            "features": features(info, dt, shape, red),
-            "configs": [list(c) for c, _ in cfgs],
-            "labels": [list(l) if l is not None else None for _, l in cfgs],
-            "ms": [med.get(i, float("nan")) for i in range(len(cfgs))],
+            "reduce": red, "shape": list(shape), "info": info, "cus": cus,
+            "features": [r4(v) for v in features(info, dt, shape, red)],
+            "ms": [r4(med[i]) if i in med else None for i in range(len(cfgs))],
             "best": best, "best_ms": med[best], "default_ms": med[len(cfgs) - 1], "mode": mode,
-            "tune_seconds": time.perf_counter() - t0}
+            "tune_seconds": round(time.perf_counter() - t0, 4)}
+
+
+def record_grid(r):
+    """The (config, labels) grid a database record's times refer to."""
+    return grid(r["reduce"], r["dtype"], r.get("cus", 256))
 
 
 def load_db(path):
