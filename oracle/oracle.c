@@ -33,8 +33,13 @@
  *     a +- b: mu_a + mu_b + |v|    a*b: mu_a|b| + |a|mu_b + |v|
  *     a/b: (mu_a + |v| mu_b)/|b| + |v|      -a, |a|: mu_a
  *     exp(a): |v|(mu_a + f)        sqrt(a): min(mu_a/(2|v|), sqrt(mu_a/u_c)) + |v|
+ *     log(a): mu_a/|a| + f|v| + f   tanh(a): (1 - v^2) mu_a + f|v|
+ *     pow(a, k) (k a constant): |k a^(k-1)| mu_a + f|v|
+ *     a > b: 0 (1 or 0; the comparison itself is exact)
+ *     conversion to FP32 storage: mu_a + |v|
  *     sum of n terms t_i: sum mu_i + (ceil(log2 n) + 2) sum |t_i|
- * where f is the allowance for the device exp (f = 2 allows 1 ulp).
+ * where f is the allowance for a device transcendental (f = 2 allows 1 ulp;
+ * log also gets an absolute allowance of f units, for results near 0).
  *
  * Integer trees (u32) are evaluated in uint64 with every operation reduced
  * mod 2^32 (C unsigned semantics).
@@ -50,7 +55,9 @@
 enum { OR_F32 = 0, OR_F64 = 1, OR_BF16 = 2, OR_F16 = 3, OR_U32 = 4 };
 enum {
   OR_LEAF = 0, OR_CONST = 1, OR_ADD = 2, OR_SUB = 3, OR_MUL = 4, OR_DIV = 5,
-  OR_NEG = 6, OR_ABS = 7, OR_EXP = 8, OR_SQRT = 9, OR_XOR = 10
+  OR_NEG = 6, OR_ABS = 7, OR_EXP = 8, OR_SQRT = 9, OR_XOR = 10,
+  /* the paper's benchmark expressions (Sec. 4) add these */
+  OR_LOG = 11, OR_TANH = 12, OR_POW = 13, OR_GT = 14, OR_TOF32 = 15
 };
 enum { OR_NONE = 0, OR_ACCU = 1, OR_COLSUM = 2, OR_ROWSUM = 3, OR_NORM = 4 };
 enum { OR_OK = 0, OR_EBAD = -1, OR_ENOMEM = -2 };
@@ -143,7 +150,7 @@ static int const_exact(double c, double u_c) {
  * (input index for OR_LEAF), cst (value for OR_CONST). */
 static void eval_node(int k, const int32_t* op, const int32_t* ca,
                       const int32_t* cb, const int32_t* leaf, const double* cst,
-                      const void* const* inputs, int dtype, int64_t e0,
+                      const void* const* inputs, const int* dtypes, int64_t e0,
                       int64_t len, double** V, double** M, double u_c,
                       double fexp) {
   double* v = V[k];
@@ -156,8 +163,9 @@ static void eval_node(int k, const int32_t* op, const int32_t* ca,
   switch (op[k]) {
     case OR_LEAF: {
       const void* p = inputs[leaf[k]];
+      const int dt = dtypes[leaf[k]];
 #pragma omp parallel for schedule(static)
-      for (i = 0; i < len; ++i) { v[i] = widen(dtype, p, e0 + i); m[i] = 0.0; }
+      for (i = 0; i < len; ++i) { v[i] = widen(dt, p, e0 + i); m[i] = 0.0; }
       break;
     }
     case OR_CONST: {
@@ -218,6 +226,35 @@ static void eval_node(int k, const int32_t* op, const int32_t* ca,
         m[i] = (lin < hol ? lin : hol) + fabs(v[i]);
       }
       break;
+    case OR_LOG:
+#pragma omp parallel for schedule(static)
+      for (i = 0; i < len; ++i) {
+        v[i] = log(va[i]);
+        m[i] = ma[i] / fabs(va[i]) + fexp * fabs(v[i]) + fexp;
+      }
+      break;
+    case OR_TANH:
+#pragma omp parallel for schedule(static)
+      for (i = 0; i < len; ++i) {
+        v[i] = tanh(va[i]);
+        m[i] = (1.0 - v[i] * v[i]) * ma[i] + fexp * fabs(v[i]);
+      }
+      break;
+    case OR_POW:  /* b is a constant exponent */
+#pragma omp parallel for schedule(static)
+      for (i = 0; i < len; ++i) {
+        v[i] = pow(va[i], vb[i]);
+        m[i] = fabs(vb[i] * pow(va[i], vb[i] - 1.0)) * ma[i] + fexp * fabs(v[i]);
+      }
+      break;
+    case OR_GT:
+#pragma omp parallel for schedule(static)
+      for (i = 0; i < len; ++i) { v[i] = va[i] > vb[i] ? 1.0 : 0.0; m[i] = 0.0; }
+      break;
+    case OR_TOF32:
+#pragma omp parallel for schedule(static)
+      for (i = 0; i < len; ++i) { v[i] = (double)(float)va[i]; m[i] = ma[i] + fabs(v[i]); }
+      break;
   }
 }
 
@@ -229,9 +266,9 @@ static int check_tree(int n_nodes, const int32_t* op, const int32_t* a,
     if (o == OR_LEAF) {
       if (leaf[k] < 0 || leaf[k] >= n_inputs) return 0;
     } else if (o == OR_CONST) {
-    } else if (o >= OR_ADD && o <= OR_DIV) {
+    } else if ((o >= OR_ADD && o <= OR_DIV) || o == OR_POW || o == OR_GT) {
       if (a[k] < 0 || a[k] >= k || b[k] < 0 || b[k] >= k) return 0;
-    } else if (o >= OR_NEG && o <= OR_SQRT) {
+    } else if ((o >= OR_NEG && o <= OR_SQRT) || o == OR_LOG || o == OR_TANH || o == OR_TOF32) {
       if (a[k] < 0 || a[k] >= k) return 0;
     } else {
       return 0;
@@ -242,7 +279,8 @@ static int check_tree(int n_nodes, const int32_t* op, const int32_t* a,
 
 /*
  * Evaluate a floating-point tree (root = last node) over an n_rows x n_cols
- * column-major operand set and optionally reduce it.
+ * column-major operand set and optionally reduce it.  dtypes[q] is the
+ * storage type of input q (u32 inputs widen to their integer value).
  *   reduce OR_NONE:   out[n], mu[n]            (n = n_rows * n_cols)
  *          OR_ACCU:   out[0] = sum of all elements
  *          OR_COLSUM: out[n_cols], column sums
@@ -253,10 +291,11 @@ static int check_tree(int n_nodes, const int32_t* op, const int32_t* a,
  */
 int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
             const int32_t* leaf, const double* cst, int n_inputs,
-            const void* const* inputs, int dtype, int64_t n_rows,
+            const void* const* inputs, const int* dtypes, int64_t n_rows,
             int64_t n_cols, int reduce, double u_c, double fexp, double* out,
             double* mu) {
-  if (dtype == OR_U32 || dtype < 0 || dtype > OR_F16) return OR_EBAD;
+  for (int q = 0; q < n_inputs; ++q)
+    if (dtypes[q] < 0 || dtypes[q] > OR_U32) return OR_EBAD;
   if (n_rows < 0 || n_cols < 0 || reduce < OR_NONE || reduce > OR_NORM) return OR_EBAD;
   if (!check_tree(n_nodes, op, a, b, leaf, n_inputs)) return OR_EBAD;
   const int64_t n = n_rows * n_cols;
@@ -281,7 +320,7 @@ int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
   for (int64_t e0 = 0; e0 < n; e0 += chunk) {
     const int64_t len = (n - e0) < chunk ? (n - e0) : chunk;
     for (int k = 0; k < n_nodes; ++k)
-      eval_node(k, op, a, b, leaf, cst, inputs, dtype, e0, len, V, M, u_c, fexp);
+      eval_node(k, op, a, b, leaf, cst, inputs, dtypes, e0, len, V, M, u_c, fexp);
     const double* v = V[root];
     const double* m = M[root];
     if (reduce == OR_NONE) {

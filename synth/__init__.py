@@ -22,7 +22,7 @@ _SO = os.path.join(_HERE, "libsynth.so")
 DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3, "u32": 4}
 NP_STORAGE = {"f32": np.float32, "f64": np.float64, "bf16": np.uint16,
               "f16": np.float16, "u32": np.uint32}
-DISTS = {"uniform": 0, "lognormal": 1, "uint31": 2, "ones": 3}
+DISTS = {"uniform": 0, "lognormal": 1, "uint31": 2, "ones": 3, "uniform12": 4}
 
 # Per-workload seeds and tensor ids (X=0, Y=1, W=2, further inputs 3, 4, ...).
 SEED = {"small": 1, "matrix": 2, "precision": 3, "batch": 4,
@@ -72,9 +72,9 @@ def fill(seed: int, tensor: int, n: int, dtype: str = "f32", dist: str = "unifor
          return_saturations: bool = False):
     """Elements [start, start+n) of tensor `tensor` under seed `seed`.
 
-    dist: "uniform" (U[-1,1]), "lognormal" (magnitude exp(param*N(0,1)),
-    random sign; param is sigma), "uint31" (u32 in [0,2^31)), "ones"
-    (every element equals param).  FP16 values beyond 65504 saturate."""
+    dist: "uniform" (U[-1,1]), "uniform12" (U[1,2)), "lognormal" (magnitude
+    exp(param*N(0,1)), random sign; param is sigma), "uint31" (u32 in
+    [0,2^31)), "ones" (every element equals param).  FP16 values beyond 65504 saturate."""
     if dist == "lognormal" and param == 0.0:
         param = 3.0
     if out is None:

@@ -23,7 +23,7 @@
 #define TGAMMA 0xD1B54A32D192ED03ULL
 
 enum { SY_F32 = 0, SY_F64 = 1, SY_BF16 = 2, SY_F16 = 3, SY_U32 = 4 };
-enum { SY_UNIFORM = 0, SY_LOGNORMAL = 1, SY_UINT31 = 2, SY_ONES = 3 };
+enum { SY_UNIFORM = 0, SY_LOGNORMAL = 1, SY_UINT31 = 2, SY_ONES = 3, SY_UNIFORM12 = 4 };
 
 static inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -111,7 +111,7 @@ static int store(int dtype, void* out, int64_t i, double v) {
 
 /* Fill out[0..n) with elements [start, start+n) of tensor `tensor`.
  * dist: SY_UNIFORM (U[-1,1]), SY_LOGNORMAL (sigma = param, random sign),
- * SY_UINT31 (u32 in [0,2^31)), SY_ONES (value = param).  Returns the number
+ * SY_UINT31 (u32 in [0,2^31)), SY_ONES (value = param), SY_UNIFORM12 (U[1,2)).  Returns the number
  * of FP16 saturations, or -1 for an unsupported combination. */
 int64_t synth_fill(uint64_t seed_cfg, uint64_t tensor, int dist, double param,
                    int dtype, int64_t start, int64_t n, void* out) {
@@ -136,6 +136,8 @@ int64_t synth_fill(uint64_t seed_cfg, uint64_t tensor, int dist, double param,
     double v;
     if (dist == SY_UNIFORM) {
       v = draw_uniform(synth_draw(seed_cfg, tensor, k));
+    } else if (dist == SY_UNIFORM12) { /* U[1,2): 1 + (r >> 11) * 2^-53, exact in FP64 */
+      v = 1.0 + (double)(synth_draw(seed_cfg, tensor, k) >> 11) * 0x1p-53;
     } else if (dist == SY_LOGNORMAL) {
       v = draw_lognormal(synth_draw(seed_cfg, tensor, 3 * k),
                          synth_draw(seed_cfg, tensor, 3 * k + 1),

@@ -285,3 +285,74 @@ def test_f16_overflow_reading():
     assert ok.all()
     ok, _ = oracle.check(np.array([65504.0, 65504.0, -65504.0, 1.0]), v, mu, "f16", out_dtype="f16")
     assert list(ok) == [True, False, False, True]
+
+
+# ---- the paper's benchmark expressions (Sec. 4) -----------------------------
+
+def test_paper_ops_against_libm_and_identities():
+    x = np.linspace(-3, 3, 6001)
+    P = oracle.paper_expr
+    v, _ = oracle.evaluate(oracle.log(X), [np.exp(x)], "f64")
+    assert np.allclose(v, x, rtol=0, atol=1e-15)
+    v, _ = oracle.evaluate(oracle.tanh(X), [x], "f64")
+    assert np.allclose(v, np.tanh(x), rtol=4.5e-16, atol=0) and v[3000] == 0.0
+    v, _ = oracle.evaluate(oracle.pow_(X, 2), [x], "f64")
+    assert np.allclose(v, x * x, rtol=2.3e-16, atol=0)
+    v, _ = oracle.evaluate(P("relu"), [x], "f64")              # X % (X > 0) = max(X, 0)
+    assert np.array_equal(v, np.maximum(x, 0))
+    v1, _ = oracle.evaluate(P("sigmoid"), [x], "f64")
+    v2, _ = oracle.evaluate(P("sigmoid"), [-x], "f64")
+    assert np.allclose(v1 + v2, 1.0, rtol=0, atol=6e-16) and v1[3000] == 0.5
+    for beta in (0.5, 1.0, 1.75):
+        v, _ = oracle.evaluate(P("swish", beta=beta), [x], "f64")
+        assert np.allclose(v, x / (1 + np.exp(-beta * x)), rtol=1e-15, atol=0)
+    g1, _ = oracle.evaluate(P("gelu"), [x], "f64")              # gelu(x) - gelu(-x) = x
+    g2, _ = oracle.evaluate(P("gelu"), [-x], "f64")
+    assert np.allclose(g1 - g2, x, rtol=0, atol=1e-15) and g1[3000] == 0.0
+    y = synth.fill(1, 1, x.size, "f64")
+    v, _ = oracle.evaluate(oracle.conv_to_f32(X), [y], "f64")
+    assert np.array_equal(v, y.astype(np.float32).astype(np.float64))
+
+
+def test_expr3_and_mixed_dtypes():
+    n = 5000
+    xf = synth.fill(1, 0, n, "f32")
+    y64 = synth.fill(1, 1, n, "f64")
+    w = synth.fill(1, 2, n, "f32", "uniform12")
+    e = oracle.paper_expr("expr3")
+    v, mu = oracle.evaluate(e, [xf, y64, w], "f32", input_dtypes=["f32", "f64", "f32"])
+    x64 = xf.astype(np.float64)
+    want = 1 / (x64 * y64.astype(np.float32) + np.log(np.log(x64 + 2) * w))
+    assert np.allclose(v, want, rtol=1e-14, atol=0)
+    v0, _ = oracle.evaluate(e, [xf, np.zeros(n), w], "f32", input_dtypes=["f32", "f64", "f32"])
+    assert np.allclose(v0, 1 / np.log(np.log(x64 + 2) * w), rtol=1e-14)   # Y = 0
+
+
+def test_undefined_bound_demands_exact_agreement():
+    # X = -1: log(X + 2) = 0, log(0) = -inf and the reciprocal is -0; the
+    # running bound meets 0 * inf there and is NaN
+    x = np.array([-1.0, 0.5], np.float32)
+    y = np.array([0.25, 0.25])
+    w = np.array([1.5, 1.5], np.float32)
+    v, mu = oracle.evaluate(oracle.paper_expr("expr3"), [x, y, w], "f32",
+                            input_dtypes=["f32", "f64", "f32"])
+    assert v[0] == 0.0 and np.signbit(v[0]) and np.isnan(mu[0]) and np.isfinite(mu[1])
+    assert oracle.check(v.copy(), v, mu, "f32")[0].all()
+    bad = v.copy()
+    bad[0] = 1e-30
+    assert list(oracle.check(bad, v, mu, "f32")[0]) == [False, True]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 16])
+def test_addn_is_left_to_right_sum(k):
+    xs = [synth.fill(2, t, 3001, "f32") for t in range(k)]
+    v, mu = oracle.evaluate(oracle.addn(k), xs, "f32")
+    s = xs[0].astype(np.float64)
+    for t in xs[1:]:
+        s = s + t
+    assert np.array_equal(v, s)
+    # FP32 left-to-right accumulation passes the rule
+    s32 = xs[0].copy()
+    for t in xs[1:]:
+        s32 = (s32 + t).astype(np.float32)
+    assert oracle.check(s32, v, mu, "f32")[0].all()

@@ -102,3 +102,10 @@ def test_lognormal_heavy_tail_shape():
     g = np.log(np.abs(v)) / 3.0
     assert abs(g.mean()) < 0.01 and abs(g.std() - 1.0) < 0.01
     assert 0.45 < (v > 0).mean() < 0.55
+
+
+def test_uniform12():
+    r = synth.raw(3, 5, 2000)
+    want = 1.0 + (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    assert np.array_equal(synth.fill_f64(3, 5, 2000, "uniform12"), want)
+    assert want.min() >= 1.0 and want.max() < 2.0
