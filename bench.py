@@ -206,6 +206,46 @@ def batch_detail(fx, torch, stream, reps):
     return res
 
 
+def paper_suite_detail(fx, torch, stream, reps):
+    """The paper's expressions at its size, 10k x 10k FP32 (Sec. 4), fused;
+    and the add-N sweep N = 2..16: fused against one add kernel per operator
+    (what toolkits without fusion launch), as effective GB/s over the same
+    algorithmic bytes."""
+    import synth
+    shape, n = (10000, 10000), 10 ** 8
+    ins = []
+    for t in range(16):
+        ins.append(torch.from_numpy(synth.fill(10, t, n, "f32")).cuda())
+    Z = torch.empty(n, device="cuda")
+    T = torch.empty(n, device="cuda")
+    suite = {}
+    for name, k, sc in [("add2", 2, ()), ("add4", 4, ()), ("relu", 1, ()), ("sigmoid", 1, ()),
+                        ("swish", 1, (1.0,)), ("gelu", 1, (0.044715,))]:
+        ms = event_ms(torch, stream, lambda: fx.fx_paper_expr(name, ins[:k], Z, shape, sc,
+                                                              stream=stream), reps)
+        suite[name] = {"ms": round(ms, 4), "GB/s": round((k + 1) * 4 * n / ms / 1e6, 1)}
+    y64 = torch.from_numpy(synth.fill(10, 20, n, "f64")).cuda()
+    w = torch.from_numpy(synth.fill(10, 21, n, "f32", "uniform12")).cuda()
+    ms = event_ms(torch, stream, lambda: fx.fx_paper_expr("expr3", [ins[0], y64, w], Z, shape,
+                                                          stream=stream), reps)
+    suite["expr3"] = {"ms": round(ms, 4), "GB/s": round((4 + 8 + 4 + 4) * n / ms / 1e6, 1)}
+    del y64, w
+    sweep = {}
+    for N in range(2, 17):
+        f = event_ms(torch, stream, lambda: fx.fx_addn(ins[:N], Z, shape, stream=stream), reps)
+
+        def unfused():
+            fx.fx_op_binary("add", ins[0], ins[1], T if N > 2 else Z, stream=stream)
+            for q in range(2, N):
+                fx.fx_op_binary("add", T, ins[q], T if q < N - 1 else Z, stream=stream)
+
+        u = event_ms(torch, stream, unfused, max(3, reps // 2))
+        b = (N + 1) * 4 * n
+        sweep[N] = {"fused_GB/s": round(b / f / 1e6, 1), "unfused_GB/s": round(b / u / 1e6, 1),
+                    "speedup": round(u / f, 2)}
+    return {"expressions_10k": suite, "add_N_sweep_10k": sweep}
+
+
 PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
                   for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp")]
@@ -316,6 +356,9 @@ def main():
         detail["copy_ceiling_GB/s"] = round(copy_ceiling(fx, torch, stream), 1)
         log("bench: precision workload, 2^28 elements")
         detail["precision_2^28"] = precision_detail(fx, torch, stream, 20)
+        torch.cuda.empty_cache()
+        log("bench: the paper's expressions and add-N sweep, 10k x 10k")
+        detail["paper_suite"] = paper_suite_detail(fx, torch, stream, 10)
         torch.cuda.empty_cache()
         log("bench: batch of 4096 expressions")
         detail["batch_4096"] = batch_detail(fx, torch, stream, 20)

@@ -189,6 +189,33 @@ int fx_norm_fro_diff(fx_dtype dt, const void* X, const void* Y, fx_shape shape,
 int fx_colsum_xy(fx_dtype dt, const void* X, const void* Y, void* out, fx_shape shape,
                  void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream);
 
+/* The paper's element-wise benchmark expressions (Sec. 4) that need no
+ * transposed, submatrix or diagonal views.  Capital letters are matrices,
+ * beta and alpha scalars; % is the Schur product. */
+typedef enum {
+  FX_PAPER_ADD2 = 1,    /* Z = X + Y                       inputs {X, Y}        */
+  FX_PAPER_ADD4 = 2,    /* Z = A + B + C + D               inputs {A, B, C, D}  */
+  FX_PAPER_RELU = 3,    /* Z = X % (X > 0)                 inputs {X}           */
+  FX_PAPER_SIGMOID = 4, /* Z = 1 / (1 + exp(-X))           inputs {X}           */
+  FX_PAPER_SWISH = 5,   /* Z = X / (1 + exp(-beta * X))    inputs {X}; s[0]=beta */
+  FX_PAPER_GELU = 6,    /* Z = (X / 2) % (1 + tanh(sqrt(2/pi) * (X + alpha * pow(X, 3))))
+                           inputs {X}; s[0]=alpha; sqrt(2/pi) rounded to the compute type */
+  FX_PAPER_EXPR3 = 7    /* Z = 1 / (X % conv_to<fmat>::from(Y) + log(log(X + 2) % W))
+                           inputs {X, Y, W}; Y is stored as FP64 and converted */
+} fx_paper_expr_id;
+
+/* One of the expressions above, fused into one kernel.  dt: FX_F32 or
+ * FX_BF16 (Y of EXPR3 is always FP64).  scalars may be NULL when unused.
+ * Scalars are rounded to the compute type. */
+int fx_paper_expr(int which, fx_dtype dt, const void* const* inputs, const double* scalars,
+                  void* Z, fx_shape shape, const fx_launch* cfg, void* stream);
+
+/* Z = A1 + A2 + ... + An (1 <= n <= 16), added left to right: the add-N
+ * family of the paper's bandwidth experiment (Sec. 4), one fused kernel
+ * reading each input once.  dt: FX_F32 or FX_BF16. */
+int fx_addn(fx_dtype dt, const void* const* inputs, int32_t n, void* Z, fx_shape shape,
+            const fx_launch* cfg, void* stream);
+
 /* ---- unfused baseline: one kernel per operator ---------------------------
  * The same skeletons and launch configurations as the fused calls, but each
  * operator writes a full temporary, as toolkits without fusion do (Sec. 4). */
@@ -225,7 +252,7 @@ int fx_unfused(int expr, fx_dtype dt, const void* const* inputs, double a, void*
 
 /* ---- run-time expression tapes ------------------------------------------
  * For trees only known at run time (they cannot be C++ types).  The tree is
- * compiled on the host into a short register program that one kernel
+ * compiled on the host into a short accumulator program that one kernel
  * interprets per element; the element loop and the reductions are the same
  * skeletons as the fused calls, so a tape is also read once and written
  * once.  Operators: FX_OP_ADD/SUB/SCHUR/DIV (binary), FX_OP_NEG/ABS/EXP/SQRT
@@ -249,11 +276,38 @@ typedef struct {
 typedef struct fx_tape fx_tape;
 
 /* Compile nodes[0..n_nodes) into *out (library-owned; fx_tape_destroy frees
- * it).  Limits: 4 inputs, 128 instructions, 12 live slots (FX_E_UNSUPPORTED
- * beyond them); malformed trees give FX_E_ARG. */
+ * it).  Limits: 4 inputs, 128 instructions, 16 slots counting the inputs
+ * (FX_E_UNSUPPORTED beyond them); malformed trees give FX_E_ARG. */
 int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out);
 void fx_tape_destroy(fx_tape* t);
 int fx_tape_describe(const fx_tape* t, fx_tape_info* out);
+
+/* The instructions of a compiled tape, for inspection and host-side
+ * checking.  The machine has one accumulator `acc` and slots s[0..16);
+ * input q is preloaded in s[q] and the result is acc after the last
+ * instruction.  y is s[slot] for the _S forms and imm for the _I forms. */
+typedef enum {
+  FX_TI_LD = 0,  /* acc = s[slot] */
+  FX_TI_LDI,     /* acc = imm */
+  FX_TI_ST,      /* s[slot] = acc */
+  FX_TI_ADD_S, FX_TI_ADD_I,   /* acc = acc + y */
+  FX_TI_SUB_S, FX_TI_SUB_I,   /* acc = acc - y */
+  FX_TI_RSUB_S, FX_TI_RSUB_I, /* acc = y - acc */
+  FX_TI_MUL_S, FX_TI_MUL_I,   /* acc = acc * y (element-wise) */
+  FX_TI_DIV_S, FX_TI_DIV_I,   /* acc = acc / y */
+  FX_TI_RDIV_S, FX_TI_RDIV_I, /* acc = y / acc */
+  FX_TI_NEG, FX_TI_ABS, FX_TI_EXP, FX_TI_SQRT, /* acc = f(acc) */
+  /* modifier bits or-ed into the opcode of an instruction that reads acc:
+   * first acc = |acc|, then acc = -acc, then the operation (abs and neg
+   * nodes are folded into their consumer this way) */
+  FX_TI_ABS_IN = 0x100,
+  FX_TI_NEG_IN = 0x200
+} fx_tape_opcode;
+
+/* Copy up to `cap` instructions of t into op[] (opcode | modifier bits),
+ * slot[] and imm[] (any may be NULL when cap is 0); returns the instruction
+ * count, or a negative fx_status for a NULL tape. */
+int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, double* imm, int32_t cap);
 
 /* Evaluate tape t over inputs[0..n_inputs) (n_inputs >= the tape's inputs,
  * all of storage dtype dt and shape `shape`).  kind 0: element-wise, `out`

@@ -101,6 +101,8 @@ _SIGS = {
     "fx_c2_rowsum": (_I, [_I, _P, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
     "fx_norm_fro_diff": (_I, [_I, _P, _P, Shape, _P, _P, _SZ, _LP, _P]),
     "fx_colsum_xy": (_I, [_I, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
+    "fx_paper_expr": (_I, [_I, _I, ctypes.POINTER(_P), ctypes.POINTER(_D), _P, Shape, _LP, _P]),
+    "fx_addn": (_I, [_I, ctypes.POINTER(_P), ctypes.c_int32, _P, Shape, _LP, _P]),
     "fx_op_unary": (_I, [_I, _I, _P, _P, _I64, _LP, _P]),
     "fx_op_binary": (_I, [_I, _I, _P, _P, _P, _I64, _LP, _P]),
     "fx_op_scalar": (_I, [_I, _I, _P, _D, _P, _I64, _LP, _P]),
@@ -110,6 +112,7 @@ _SIGS = {
     "fx_tape_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, ctypes.POINTER(_P)]),
     "fx_tape_destroy": (None, [_P]),
     "fx_tape_describe": (_I, [_P, ctypes.POINTER(TapeInfo)]),
+    "fx_tape_program": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int32]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
@@ -325,6 +328,23 @@ def fx_colsum_xy(X, Y, out, shape, ws=None, cfg=None, stream=None):
                                     p, nb, _cfg(cfg), _stream(stream)))
 
 
+PAPER = {"add2": 1, "add4": 2, "relu": 3, "sigmoid": 4, "swish": 5, "gelu": 6, "expr3": 7}
+
+
+def fx_paper_expr(which, inputs, Z, shape, scalars=(), cfg=None, stream=None, dt=None):
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    sc = (_D * max(1, len(scalars)))(*scalars) if scalars else None
+    dt = dtype_code(inputs[0]) if dt is None else dt
+    return check(lib().fx_paper_expr(PAPER.get(which, which), dt, arr, sc, _ptr(Z), _shape(shape),
+                                     _cfg(cfg), _stream(stream)))
+
+
+def fx_addn(inputs, Z, shape, cfg=None, stream=None):
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    return check(lib().fx_addn(dtype_code(inputs[0]), arr, len(inputs), _ptr(Z), _shape(shape),
+                               _cfg(cfg), _stream(stream)))
+
+
 # ---- unfused baseline -----------------------------------------------------------------
 
 
@@ -389,6 +409,9 @@ class Tape:
     def info(self) -> dict:
         return fx_tape_describe(self)
 
+    def program(self):
+        return fx_tape_program(self)
+
 
 def fx_tape_create(nodes) -> Tape:
     return Tape(nodes)
@@ -404,6 +427,29 @@ def fx_tape_describe(tape: Tape) -> dict:
     info = TapeInfo()
     check(lib().fx_tape_describe(tape.handle, ctypes.byref(info)))
     return info.as_dict()
+
+
+TAPE_OPCODES = ("LD", "LDI", "ST", "ADD_S", "ADD_I", "SUB_S", "SUB_I", "RSUB_S", "RSUB_I",
+                "MUL_S", "MUL_I", "DIV_S", "DIV_I", "RDIV_S", "RDIV_I", "NEG", "ABS", "EXP",
+                "SQRT")
+TAPE_ABS_IN, TAPE_NEG_IN = 0x100, 0x200
+
+
+def fx_tape_program(tape: Tape):
+    """The compiled instructions as a list of (opcode name, slot, immediate);
+    input modifiers are appended to the name ("SQRT|abs": sqrt(|acc|))."""
+    n = lib().fx_tape_program(tape.handle, None, None, None, 0)
+    if n < 0:
+        check(-n)
+    op = (ctypes.c_uint16 * max(1, n))()
+    slot = (ctypes.c_uint8 * max(1, n))()
+    imm = (ctypes.c_double * max(1, n))()
+    lib().fx_tape_program(tape.handle, op, slot, imm, n)
+
+    def name(code):
+        mods = ("|abs" if code & TAPE_ABS_IN else "") + ("|neg" if code & TAPE_NEG_IN else "")
+        return TAPE_OPCODES[code & 0xFF] + mods
+    return [(name(op[i]), slot[i], imm[i]) for i in range(n)]
 
 
 def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stream=None,

@@ -4,6 +4,11 @@
 
 Flags: -O3, no fast-math (IEEE divide/sqrt and denormals kept), packed FP32
 instructions disabled on the device (-target-feature -packed-fp32-ops).
+The tape interpreters (fx_tape*.hip, fx_batch.hip) also keep branches on
+wave-uniform values as plain scalar branches instead of structurizing them
+(-structurizecfg-skip-uniform-regions): the opcode switch then compiles to a
+branch tree whose cases update the accumulator in place, without the flow
+blocks and merge copies that cost four moves per interpreted instruction.
 """
 from __future__ import annotations
 
@@ -27,12 +32,20 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+UNIFORM_BRANCHES = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+
+
+def _flags_for(src: str) -> list[str]:
+    base = os.path.basename(src)
+    if base.startswith("fx_tape") or base == "fx_batch.hip":
+        return UNIFORM_BRANCHES
+    return []
 
 
 def _compile(src: str, extra: list[str], objdir: str) -> tuple[str, float]:
     obj = os.path.join(objdir, os.path.basename(src) + ".o")
     t = time.time()
-    cmd = [HIPCC] + CFLAGS + extra + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + _flags_for(src) + extra + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the device-only feature name: drop that line
     err = "\n".join(l for l in (p.stderr or "").splitlines()

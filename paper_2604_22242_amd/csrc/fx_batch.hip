@@ -25,7 +25,7 @@ struct batch_desc {
   int64_t first_tile;
 };
 
-template <class T, int N, int EPT>
+template <class T, int N, int EPT, int SLOTS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restrict__ descs,
                                                    const tape_prog* __restrict__ progs,
                                                    const uint32_t* __restrict__ tile_item,
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
   for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint32_t it = tile_item[t];
     const batch_desc d = descs[it];
-    TapeExpr<T, true> x;
+    TapeExpr<T, true, SLOTS> x;
 #pragma unroll
     for (int q = 0; q < kTapeMaxIn; ++q) x.p[q] = static_cast<const T*>(d.in[q]);
     x.n_rows = d.n;
@@ -125,6 +125,7 @@ struct fx_batch {
   hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
   int vec;
+  bool small_slots;  // every program fits the 8-slot file
 };
 
 static void batch_free(fx_batch* b) {
@@ -164,9 +165,14 @@ static int batch_run(fx_batch* b, hipStream_t st) {
   return batch_dispatch(b->dt, b->vec, I.ept, [&](auto tg, auto Nc, auto Ec) {
     using T = typename decltype(tg)::type;
     constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
-    hipLaunchKernelGGL((k_batch<T, N, EPT>), dim3(I.grid), dim3(I.block), 0, st, b->d_descs,
-                       b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems, b->d_partials,
-                       b->d_counters);
+    if (b->small_slots)
+      hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeSmallSlots>), dim3(I.grid), dim3(I.block), 0, st,
+                         b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
+                         b->d_partials, b->d_counters);
+    else
+      hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeMaxSlots>), dim3(I.grid), dim3(I.block), 0, st,
+                         b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
+                         b->d_partials, b->d_counters);
     return hip_check(hipGetLastError(), "k_batch launch");
   });
 }
@@ -200,6 +206,9 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   fx_batch* b = new (std::nothrow) fx_batch;
   if (!b) return fail(FX_E_ARG, "out of host memory");
   b->dt = dt;
+  b->small_slots = true;
+  for (int i = 0; i < count; ++i)
+    if (items[i].tape->prog.n_slots > kTapeSmallSlots) b->small_slots = false;
   fx_batch_info& I = b->info;
   I = fx_batch_info{};
   I.count = count;

@@ -59,13 +59,21 @@ template <> struct raw<16> { using type = unsigned int __attribute__((ext_vector
 // Load N consecutive elements at p + i (p + i aligned to N*sizeof(T)) and
 // widen them to the compute type.  NT selects the nontemporal (streaming)
 // cache policy.
+// Vectors wider than 16 bytes (a wide leaf inside an expression of a
+// narrower storage type) are read as several 16-byte loads.
 template <int N, bool NT, class T>
 __device__ __forceinline__ lanes<ct_t<T>, N> load_lanes(const T* __restrict__ p, int64_t i) {
-  using R = typename raw<N * (int)sizeof(T)>::type;
-  const R* q = reinterpret_cast<const R*>(p + i);
-  R r = NT ? __builtin_nontemporal_load(q) : *q;
+  constexpr int BYTES = N * (int)sizeof(T);
+  constexpr int CHUNK = BYTES > 16 ? 16 : BYTES;
+  constexpr int PER = CHUNK / (int)sizeof(T);  // elements per load
+  using R = typename raw<CHUNK>::type;
   T s[N];
-  __builtin_memcpy(s, &r, sizeof(R));
+#pragma unroll
+  for (int c = 0; c < N / PER; ++c) {
+    const R* q = reinterpret_cast<const R*>(p + i + c * PER);
+    R r = NT ? __builtin_nontemporal_load(q) : *q;
+    __builtin_memcpy(s + c * PER, &r, sizeof(R));
+  }
   lanes<ct_t<T>, N> out;
 #pragma unroll
   for (int j = 0; j < N; ++j) out.v[j] = static_cast<ct_t<T>>(s[j]);

@@ -21,6 +21,8 @@
 
 #include <math.h>
 
+#include <cmath>
+
 #include <type_traits>
 
 #include "fx_core.hpp"
@@ -49,6 +51,18 @@ struct leaf_info {
   bool aligned(int bytes) const { return (addr_or & (uintptr_t)(bytes - 1)) == 0; }
 };
 
+// Identity of a leaf for de-duplication: the same address read as the same
+// storage type.
+struct leaf_id {
+  const void* p;
+  size_t size;
+  int kind;
+};
+template <class T> constexpr int kind_of() {
+  return std::is_same_v<T, float> ? 0 : std::is_same_v<T, double> ? 1
+       : std::is_same_v<T, bf16_t> ? 2 : std::is_same_v<T, f16_t> ? 3 : 4;
+}
+
 // ---- leaves ----------------------------------------------------------------
 
 // A read-only, non-owning view of a dense column-major device matrix.
@@ -65,6 +79,17 @@ template <class T> struct Leaf : expr_tag {
     return load_lanes<N, NT>(p, i);
   }
   void collect(leaf_info& li) const { li.add(p, n_rows, n_cols); }
+  // two-phase evaluation (see Fused below): this leaf is register leaf OFF
+  static constexpr int kLeaves = 1;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R* regs, const uint8_t* alias, int64_t i) const {
+    if (alias[OFF] == OFF) regs[OFF] = load_lanes<N, NT>(p, i);
+  }
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R* regs, int64_t) const {
+    return regs[OFF];
+  }
+  void leaf_ids(leaf_id* out, int& k) const { out[k++] = leaf_id{p, sizeof(T), kind_of<T>()}; }
 };
 
 // Non-owning views handed to the front end (Armadillo-style dmat / dvec).
@@ -103,6 +128,24 @@ struct op_sqrt {
   __device__ static float apply(float a) { return ::sqrtf(a); }
   __device__ static double apply(double a) { return ::sqrt(a); }
 };
+struct op_log {
+  __device__ static float apply(float a) { return ::logf(a); }
+  __device__ static double apply(double a) { return ::log(a); }
+};
+struct op_tanh {
+  __device__ static float apply(float a) { return ::tanhf(a); }
+  __device__ static double apply(double a) { return ::tanh(a); }
+};
+// a^k for a scalar exponent k
+struct op_pow {
+  __device__ static float apply(float a, float k) { return ::powf(a, k); }
+  __device__ static double apply(double a, double k) { return ::pow(a, k); }
+};
+// a > b as 1 or 0 of the compute type (a relational operator yields a 0/1
+// matrix that the Schur product can use)
+struct op_gt {
+  template <class C> __device__ static C apply(C a, C b) { return a > b ? C(1) : C(0); }
+};
 
 // ---- inner nodes ---------------------------------------------------------------
 
@@ -119,6 +162,19 @@ template <class Op, class A> struct Unary : expr_tag {
     return x;
   }
   void collect(leaf_info& li) const { a.collect(li); }
+  static constexpr int kLeaves = A::kLeaves;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R* regs, const uint8_t* alias, int64_t i) const {
+    a.template gather<OFF, N, NT>(regs, alias, i);
+  }
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R* regs, int64_t i) const {
+    lanes<ct, N> x = a.template at_regs<OFF, N, NT>(regs, i);
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = Op::apply(x.v[j]);
+    return x;
+  }
+  void leaf_ids(leaf_id* out, int& k) const { a.leaf_ids(out, k); }
 };
 
 template <class Op, class A, class B> struct Binary : expr_tag {
@@ -138,16 +194,52 @@ template <class Op, class A, class B> struct Binary : expr_tag {
     return x;
   }
   void collect(leaf_info& li) const { a.collect(li); b.collect(li); }
+  static constexpr int kLeaves = A::kLeaves + B::kLeaves;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R* regs, const uint8_t* alias, int64_t i) const {
+    a.template gather<OFF, N, NT>(regs, alias, i);
+    b.template gather<OFF + A::kLeaves, N, NT>(regs, alias, i);
+  }
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R* regs, int64_t i) const {
+    lanes<ct, N> x = a.template at_regs<OFF, N, NT>(regs, i);
+    lanes<ct, N> y = b.template at_regs<OFF + A::kLeaves, N, NT>(regs, i);
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = Op::apply(x.v[j], y.v[j]);
+    return x;
+  }
+  void leaf_ids(leaf_id* out, int& k) const { a.leaf_ids(out, k); b.leaf_ids(out, k); }
 };
 
 // k op child (LEFT = true) or child op k: the scalar node of Sec. 3, which
 // adds `aux` to the child's element access.
+// Scalar-operand shortcuts chosen on the host when the node is built (the
+// scalar is a run-time value): x / k with k a power of two whose reciprocal
+// is exact becomes x * (1/k), bitwise the same; pow(x, k) for k = 1..4 is a
+// product of x's (k = 2 is correctly rounded like pow; k = 3, 4 take two
+// roundings, inside pow's error allowance).
+enum : int32_t { SC_PLAIN = 0, SC_MUL_INV = 1, SC_POW1 = 2, SC_POW2, SC_POW3, SC_POW4 };
+
 template <class Op, class A, bool LEFT> struct Scalar : expr_tag {
   using ct = typename A::ct;
   using storage = typename A::storage;
   A a;
   ct k;
+  ct aux = ct(0);          // 1/k for SC_MUL_INV
+  int32_t mode = SC_PLAIN;
   __device__ __forceinline__ ct apply1(ct x) const {
+    if constexpr (std::is_same_v<Op, op_div> && !LEFT) {
+      if (mode == SC_MUL_INV) return x * aux;
+    }
+    if constexpr (std::is_same_v<Op, op_pow>) {
+      switch (mode) {
+        case SC_POW1: return x;
+        case SC_POW2: return x * x;
+        case SC_POW3: return (x * x) * x;
+        case SC_POW4: { const ct x2 = x * x; return x2 * x2; }
+        default: break;
+      }
+    }
     return LEFT ? Op::apply(k, x) : Op::apply(x, k);
   }
   __device__ __forceinline__ ct at(int64_t i) const { return apply1(a.at(i)); }
@@ -159,7 +251,153 @@ template <class Op, class A, bool LEFT> struct Scalar : expr_tag {
     return x;
   }
   void collect(leaf_info& li) const { a.collect(li); }
+  static constexpr int kLeaves = A::kLeaves;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R* regs, const uint8_t* alias, int64_t i) const {
+    a.template gather<OFF, N, NT>(regs, alias, i);
+  }
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R* regs, int64_t i) const {
+    lanes<ct, N> x = a.template at_regs<OFF, N, NT>(regs, i);
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = apply1(x.v[j]);
+    return x;
+  }
+  void leaf_ids(leaf_id* out, int& k) const { a.leaf_ids(out, k); }
 };
+
+// conv_to<To>::from(child): the child's elements converted to compute type To
+// (rounded to nearest-even when narrowing), so a leaf of another storage type
+// can take part in the expression.
+template <class To, class A> struct Convert : expr_tag {
+  using ct = To;
+  using storage = To;
+  A a;
+  __device__ __forceinline__ ct at(int64_t i) const { return static_cast<To>(a.at(i)); }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<typename A::ct, N> x = a.template at_vec<N, NT>(i);
+    lanes<ct, N> r;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r.v[j] = static_cast<To>(x.v[j]);
+    return r;
+  }
+  void collect(leaf_info& li) const { a.collect(li); }
+  // another compute type below: evaluated in place, its leaves not shared
+  static constexpr int kLeaves = 0;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R*, const uint8_t*, int64_t) const {}
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R*, int64_t i) const {
+    return at_vec<N, NT>(i);
+  }
+  void leaf_ids(leaf_id*, int&) const {}
+};
+
+// A1 + A2 + ... + AK over K leaves of one storage type, added left to right
+// as the nested binary form would (the add-N expressions of Sec. 4).
+template <class T, int K> struct SumN : expr_tag {
+  using storage = T;
+  using ct = ct_t<T>;
+  const T* p[K];
+  int64_t n_rows, n_cols;
+  __device__ __forceinline__ ct at(int64_t i) const {
+    ct s = static_cast<ct>(p[0][i]);
+#pragma unroll
+    for (int q = 1; q < K; ++q) s = s + static_cast<ct>(p[q][i]);
+    return s;
+  }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<ct, N> x[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[q] = load_lanes<N, NT>(p[q], i);
+#pragma unroll
+    for (int q = 1; q < K; ++q)
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[0].v[j] = x[0].v[j] + x[q].v[j];
+    return x[0];
+  }
+  void collect(leaf_info& li) const {
+    for (int q = 0; q < K; ++q) li.add(p[q], n_rows, n_cols);
+  }
+  // its K loads are issued together already
+  static constexpr int kLeaves = 0;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R*, const uint8_t*, int64_t) const {}
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R*, int64_t i) const {
+    return at_vec<N, NT>(i);
+  }
+  void leaf_ids(leaf_id*, int&) const {}
+};
+
+// ---- reading a repeated leaf once -----------------------------------------
+//
+// An expression may name the same matrix several times ((X+Y)/(1+X%X)); each
+// occurrence is its own leaf with its own pointer, so the compiler cannot
+// merge their loads.  Fused<E> evaluates E in two phases: gather() loads
+// every register leaf whose address and storage type were not already seen
+// (in depth-first order; the host computes alias[k], the first leaf equal to
+// leaf k), the repeats are copied register to register, and at_regs()
+// evaluates the tree from those registers.  Leaf indices are fixed at
+// compile time by the traversal, so no register is indexed at run time.
+constexpr int kMaxFusedLeaves = 16;
+
+template <class E, class = void> struct leaves_of { static constexpr int value = 0; };
+template <class E> struct leaves_of<E, std::void_t<decltype(E::kLeaves)>> {
+  static constexpr int value = E::kLeaves;
+};
+
+template <class E> struct Fused : expr_tag {
+  using ct = typename E::ct;
+  using storage = typename E::storage;
+  static constexpr int L = E::kLeaves;
+  static_assert(L >= 1 && L <= kMaxFusedLeaves, "register-leaf count out of range");
+  E e;
+  uint8_t alias[L];
+
+  __device__ __forceinline__ ct at(int64_t i) const { return e.at(i); }
+  // regs[k] for the first occurrence k of a leaf, copies for the repeats
+  template <int N>
+  __device__ __forceinline__ void resolve(lanes<ct, N>* regs) const {
+#pragma unroll
+    for (int k = 1; k < L; ++k)
+#pragma unroll
+      for (int j = 0; j < k; ++j)
+        if (alias[k] == j) regs[k] = regs[j];
+  }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<ct, N> regs[L];
+    e.template gather<0, N, NT>(regs, alias, i);
+    resolve<N>(regs);
+    return e.template at_regs<0, N, NT>(regs, i);
+  }
+  void collect(leaf_info& li) const { e.collect(li); }
+};
+
+// Host: wrap E when it has two or more register leaves.
+template <class E> inline auto fuse_leaves(const E& e) {
+  if constexpr (leaves_of<E>::value >= 2 && leaves_of<E>::value <= kMaxFusedLeaves) {
+    Fused<E> f;
+    f.e = e;
+    leaf_id ids[kMaxFusedLeaves];
+    int k = 0;
+    e.leaf_ids(ids, k);
+    for (int a = 0; a < Fused<E>::L; ++a) {
+      f.alias[a] = (uint8_t)a;
+      for (int b = 0; b < a; ++b)
+        if (ids[b].p == ids[a].p && ids[b].size == ids[a].size && ids[b].kind == ids[a].kind) {
+          f.alias[a] = (uint8_t)b;
+          break;
+        }
+    }
+    return f;
+  } else {
+    return e;
+  }
+}
 
 // ---- operator overloads (host side: they build the type) -------------------------
 
@@ -172,6 +410,27 @@ template <class E> constexpr bool is_operand_v =
     std::is_same_v<std::decay_t<E>, dmat<uint32_t>>;
 template <class E> constexpr bool is_scalar_v = std::is_arithmetic_v<std::decay_t<E>>;
 
+// Host: pick the shortcut of a freshly built scalar node.
+template <class Op, class E, bool LEFT> inline Scalar<Op, E, LEFT> tune_scalar(Scalar<Op, E, LEFT> s) {
+  using C = typename E::ct;
+  if constexpr (std::is_same_v<Op, op_div> && !LEFT && std::is_floating_point_v<C>) {
+    int e = 0;
+    const C m = std::frexp(s.k, &e);  // k = m * 2^e, |m| in [0.5, 1)
+    const C inv = C(1) / s.k;
+    if ((m == C(0.5) || m == C(-0.5)) && std::isnormal(s.k) && std::isnormal(inv)) {
+      s.mode = SC_MUL_INV;
+      s.aux = inv;
+    }
+  }
+  if constexpr (std::is_same_v<Op, op_pow>) {
+    if (s.k == C(1)) s.mode = SC_POW1;
+    else if (s.k == C(2)) s.mode = SC_POW2;
+    else if (s.k == C(3)) s.mode = SC_POW3;
+    else if (s.k == C(4)) s.mode = SC_POW4;
+  }
+  return s;
+}
+
 #define FX_BINARY_OPERATOR(SYM, OP)                                                     \
   template <class A, class B, std::enable_if_t<is_operand_v<A> && is_operand_v<B>, int> = 0> \
   inline auto operator SYM(const A& a, const B& b) {                                   \
@@ -180,7 +439,7 @@ template <class E> constexpr bool is_scalar_v = std::is_arithmetic_v<std::decay_
   template <class A, class S, std::enable_if_t<is_operand_v<A> && is_scalar_v<S>, int> = 0> \
   inline auto operator SYM(const A& a, S k) {                                          \
     using E = expr_of<A>;                                                               \
-    return Scalar<OP, E, false>{{}, as_expr(a), static_cast<typename E::ct>(k)};        \
+    return tune_scalar(Scalar<OP, E, false>{{}, as_expr(a), static_cast<typename E::ct>(k)}); \
   }                                                                                     \
   template <class S, class A, std::enable_if_t<is_scalar_v<S> && is_operand_v<A>, int> = 0> \
   inline auto operator SYM(S k, const A& a) {                                          \
@@ -225,6 +484,23 @@ template <class A, std::enable_if_t<is_operand_v<A>, int> = 0>
 inline auto abs(const A& a) { return Unary<op_abs, expr_of<A>>{{}, as_expr(a)}; }
 template <class A, std::enable_if_t<is_operand_v<A>, int> = 0>
 inline auto sqrt(const A& a) { return Unary<op_sqrt, expr_of<A>>{{}, as_expr(a)}; }
+template <class A, std::enable_if_t<is_operand_v<A>, int> = 0>
+inline auto log(const A& a) { return Unary<op_log, expr_of<A>>{{}, as_expr(a)}; }
+template <class A, std::enable_if_t<is_operand_v<A>, int> = 0>
+inline auto tanh(const A& a) { return Unary<op_tanh, expr_of<A>>{{}, as_expr(a)}; }
+template <class A, class S, std::enable_if_t<is_operand_v<A> && is_scalar_v<S>, int> = 0>
+inline auto pow(const A& a, S k) {
+  using E = expr_of<A>;
+  return tune_scalar(Scalar<op_pow, E, false>{{}, as_expr(a), static_cast<typename E::ct>(k)});
+}
+template <class A, class S, std::enable_if_t<is_operand_v<A> && is_scalar_v<S>, int> = 0>
+inline auto operator>(const A& a, S k) {
+  using E = expr_of<A>;
+  return Scalar<op_gt, E, false>{{}, as_expr(a), static_cast<typename E::ct>(k)};
+}
+// conv_to<To>(A): Armadillo's conv_to<Mat<To>>::from(A)
+template <class To, class A, std::enable_if_t<is_operand_v<A>, int> = 0>
+inline auto conv_to(const A& a) { return Convert<To, expr_of<A>>{{}, as_expr(a)}; }
 
 template <class E> inline leaf_info info_of(const E& e) {
   leaf_info li;

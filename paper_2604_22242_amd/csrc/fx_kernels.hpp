@@ -61,6 +61,20 @@ __device__ __forceinline__ void eval_tile(const E& e, int64_t base, int64_t stri
   for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(base + k * stride);
 }
 
+// Fused<E>: the loads of all EPT vectors first, then the arithmetic.
+template <int N, int EPT, class E>
+__device__ __forceinline__ void eval_tile(const Fused<E>& f, int64_t base, int64_t stride,
+                                          lanes<typename E::ct, N> (&r)[EPT]) {
+  lanes<typename E::ct, N> regs[EPT][Fused<E>::L];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) f.e.template gather<0, N, kNT>(regs[k], f.alias, base + k * stride);
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    f.template resolve<N>(regs[k]);
+    r[k] = f.e.template at_regs<0, N, kNT>(regs[k], base + k * stride);
+  }
+}
+
 // ============================================================================
 // Element-wise: Z[i] = E(i), i < n.
 
@@ -69,8 +83,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_ew(E e, T* __restrict__ z, int64_
   using C = typename E::ct;
   const int64_t nv = n / N;  // whole vectors
   const int64_t tile = (int64_t)blockDim.x * EPT;
-  const int64_t ntiles = (nv + tile - 1) / tile;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // tile t exists while t * tile < nv (no 64-bit division: gfx950 has no
+  // scalar divide, and its emulation would delay every wave's first load)
+  for (int64_t t = blockIdx.x; t * tile < nv; t += gridDim.x) {
     const int64_t v0 = t * tile + threadIdx.x;
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
@@ -103,8 +118,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_full(E e, int64_t n, typename wid
   accum<C> acc;
   const int64_t nv = n / N;
   const int64_t tile = (int64_t)blockDim.x * EPT;
-  const int64_t ntiles = (nv + tile - 1) / tile;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // tile t exists while t * tile < nv (no 64-bit division: gfx950 has no
+  // scalar divide, and its emulation would delay every wave's first load)
+  for (int64_t t = blockIdx.x; t * tile < nv; t += gridDim.x) {
     const int64_t v0 = t * tile + threadIdx.x;
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
@@ -290,6 +306,7 @@ template <int V> using ic = std::integral_constant<int, V>;
 // Largest EPT compiled for an expression type (the run-time tape keeps one
 // slot file per lane in registers and caps it lower).
 template <class E> struct max_ept { static constexpr int value = 8; };
+template <class E> struct max_ept<Fused<E>> { static constexpr int value = max_ept<E>::value; };
 
 template <int MAX = 8, class F> inline int with_ept(int ept, F&& f) {
   switch (ept) {
@@ -340,7 +357,13 @@ template <class E> inline void clamp_ept(launch& L, const fx_launch* cfg) {
 
 // Z = E element-wise (Sec. 3: assignment through the copy skeleton).
 template <class E, class T>
+int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st);
+template <class E, class T>
 int eval(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
+  return eval_direct(z, fuse_leaves(e), cfg, st);
+}
+template <class E, class T>
+int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
   int64_t rows, cols;
   if (int rc = check_expr(e, &rows, &cols)) return rc;
   const int64_t n = rows * cols;
@@ -368,8 +391,16 @@ template <class D> inline D* ws_partials(void* ws, const ws_layout& W) {
 
 // out = finish(sum map(E)) as FP64 (u64 for u32 expressions).
 template <class M, class E>
+int reduce_full_direct(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
+                       hipStream_t st);
+template <class M, class E>
 int reduce_full(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
                 hipStream_t st) {
+  return reduce_full_direct<M>(fuse_leaves(e), out, ws, ws_bytes, cfg, st);
+}
+template <class M, class E>
+int reduce_full_direct(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
+                       hipStream_t st) {
   using T = typename E::storage;
   using D = typename wide<typename E::ct>::type;
   int64_t rows, cols;
@@ -397,8 +428,16 @@ int reduce_full(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launc
 
 // sum(E, 0) or sum(E, 1) into out (accumulator dtype O).
 template <class O, class E>
+int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
+                      const fx_launch* cfg, hipStream_t st);
+template <class O, class E>
 int reduce_dim(int kind, const E& e, O* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
                hipStream_t st) {
+  return reduce_dim_direct(kind, fuse_leaves(e), out, ws, ws_bytes, cfg, st);
+}
+template <class O, class E>
+int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
+                      const fx_launch* cfg, hipStream_t st) {
   using T = typename E::storage;
   using D = typename wide<typename E::ct>::type;
   int64_t rows, cols;

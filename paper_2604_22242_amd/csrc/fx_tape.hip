@@ -16,18 +16,6 @@ bool is_unary(int op) {
 bool is_binary(int op) {
   return op == FX_OP_ADD || op == FX_OP_SUB || op == FX_OP_SCHUR || op == FX_OP_DIV;
 }
-uint8_t tape_op(int op) {
-  switch (op) {
-    case FX_OP_ADD: return T_ADD;
-    case FX_OP_SUB: return T_SUB;
-    case FX_OP_SCHUR: return T_MUL;
-    case FX_OP_DIV: return T_DIV;
-    case FX_OP_NEG: return T_NEG;
-    case FX_OP_ABS: return T_ABS;
-    case FX_OP_EXP: return T_EXP;
-    default: return T_SQRT;
-  }
-}
 int op_index(int op) {  // position in fx_tape_info::op_count
   switch (op) {
     case FX_OP_ADD: return 0;
@@ -41,13 +29,22 @@ int op_index(int op) {  // position in fx_tape_info::op_count
   }
 }
 
-// An operand of an instruction: a slot or an immediate.
+// Where a node's value is: in the accumulator (and, for a node used more
+// than once, also in `slot`), in a slot (inputs, stored values), or an
+// immediate constant.
+enum where { IN_ACC, IN_SLOT, IMMED };
+
 struct operand {
-  bool imm = false;
+  where w = IN_SLOT;
   int slot = -1;
   double value = 0;
 };
 
+// Accumulator code generation.  A node's code leaves its value in the
+// accumulator.  A binary node whose operands both need code evaluates the
+// one needing more slots first (Sethi-Ullman order for an accumulator
+// machine), stores it, evaluates the other and combines them with the
+// operand order kept through the reversed forms (y - acc, y / acc).
 struct compiler {
   const fx_node* nodes;
   int n;
@@ -71,23 +68,64 @@ struct compiler {
     max_slot = std::max(max_slot, next_slot);
     return s;
   }
+  // One use of node k is consumed; its slot is free after the last.
   void release(int k) {
-    if (--uses[k] == 0 && !result[k].imm && result[k].slot >= n_in)
+    if (--uses[k] == 0 && result[k].slot >= n_in && result[k].w != IMMED)
       free_slots.push_back(result[k].slot);
   }
-  void emit_ins(uint8_t op, int dst, const operand& a, const operand* b) {
+  // abs / neg of the accumulator not yet applied: they become input
+  // modifiers of the next instruction that reads it
+  uint16_t pending = 0;
+  void modify(uint16_t m) {
+    if (m == kAbsIn) pending = kAbsIn;  // |x|, |-x|, |-|x|| all equal |x|
+    else pending ^= kNegIn;
+  }
+  void flush() {  // apply pending modifiers as instructions of their own
+    const uint16_t m = pending;
+    pending = 0;
+    if (m & kAbsIn) emit_ins(A_ABS);
+    if (m & kNegIn) emit_ins(A_NEG);
+  }
+  void emit_ins(uint8_t op, int slot = 0, double k = 0.0) {
+    if (op == A_LD || op == A_LDI) {
+      if (pending) flush();  // never happens for a tree: acc is consumed first
+    }
     if (prog->n_ins >= kTapeMaxIns) {
       if (status == FX_OK) status = fail(FX_E_UNSUPPORTED, "tape longer than %d instructions", kTapeMaxIns);
       return;
     }
     tape_ins& I = prog->ins[prog->n_ins++];
-    I.op = op;
-    I.dst = (uint8_t)dst;
-    I.a = a.imm ? kImm : (uint8_t)a.slot;
-    I.b = (b && !b->imm) ? (uint8_t)b->slot : kImm;
-    const double k = a.imm ? a.value : (b && b->imm ? b->value : 0.0);
+    I = tape_ins{};
+    I.op = (uint16_t)(op | ((op == A_LD || op == A_LDI) ? 0 : pending));
+    if (op != A_LD && op != A_LDI) pending = 0;
+    I.a = (uint16_t)slot;
     I.kf = (float)k;
     I.kd = k;
+  }
+  // Does evaluating node k emit code (and so overwrite the accumulator)?
+  bool needs_code(int k) const {
+    return !done[k] && nodes[k].op != FX_OP_LEAF && nodes[k].op != FX_OP_CONST;
+  }
+  void load(const operand& o) {
+    if (o.w == IMMED) emit_ins(A_LDI, 0, o.value);
+    else if (o.w == IN_SLOT) emit_ins(A_LD, o.slot);
+  }
+  // acc = x OP y where one of x, y is in the accumulator (acc_left says
+  // which); the other is a slot or an immediate.
+  void combine(int op, bool acc_left, const operand& other) {
+    const bool imm = other.w == IMMED;
+    uint8_t code;
+    switch (op) {
+      case FX_OP_ADD: code = imm ? A_ADD_I : A_ADD_S; break;            // commutes exactly
+      case FX_OP_SCHUR: code = imm ? A_MUL_I : A_MUL_S; break;          // commutes exactly
+      case FX_OP_SUB:
+        code = acc_left ? (imm ? A_SUB_I : A_SUB_S) : (imm ? A_RSUB_I : A_RSUB_S);
+        break;
+      default:  // FX_OP_DIV
+        code = acc_left ? (imm ? A_DIV_I : A_DIV_S) : (imm ? A_RDIV_I : A_RDIV_S);
+        break;
+    }
+    emit_ins(code, imm ? 0 : other.slot, imm ? other.value : 0.0);
   }
   operand emit(int k) {
     if (done[k]) return result[k];
@@ -96,36 +134,57 @@ struct compiler {
     if (nd.op == FX_OP_LEAF) {
       r.slot = nd.input;
     } else if (nd.op == FX_OP_CONST) {
-      r.imm = true;
+      r.w = IMMED;
       r.value = nd.value;
     } else if (is_unary(nd.op)) {
       operand a = emit(nd.a);
+      if (a.w != IN_ACC) load(a);
       release(nd.a);
-      int dst = alloc();
-      emit_ins(tape_op(nd.op), dst, a, nullptr);
-      r.slot = dst;
+      if (nd.op == FX_OP_ABS) modify(kAbsIn);
+      else if (nd.op == FX_OP_NEG) modify(kNegIn);
+      else emit_ins(nd.op == FX_OP_EXP ? A_EXP : A_SQRT);
+      r.w = IN_ACC;
     } else {
-      // the operand needing more slots first (Sethi-Ullman order)
       const bool a_first = need[nd.a] >= need[nd.b];
-      operand a, b;
-      if (a_first) { a = emit(nd.a); b = emit(nd.b); }
-      else { b = emit(nd.b); a = emit(nd.a); }
-      int mov = -1;
-      if (a.imm && b.imm) {  // two immediates: materialise one
-        mov = alloc();
-        emit_ins(T_MOV, mov, a, nullptr);
-        a.imm = false;
-        a.slot = mov;
+      const int f = a_first ? nd.a : nd.b, g = a_first ? nd.b : nd.a;
+      operand x = emit(f);
+      int spill = -1;
+      if (x.w == IN_ACC && needs_code(g)) {  // keep x while g is computed
+        if (x.slot < 0) {
+          x.slot = spill = alloc();
+          emit_ins(A_ST, x.slot);
+        }
+        x.w = IN_SLOT;
+      }
+      operand y = emit(g);
+      // x: first-evaluated operand, y: second; map back to (left, right)
+      const operand& L = a_first ? x : y;
+      const operand& R = a_first ? y : x;
+      if (L.w == IN_ACC) {
+        combine(nd.op, true, R);
+      } else if (R.w == IN_ACC) {
+        combine(nd.op, false, L);
+      } else if (L.w == IN_SLOT || R.w == IMMED) {
+        load(L);
+        combine(nd.op, true, R);
+      } else {  // L immediate, R in a slot
+        load(R);
+        combine(nd.op, false, L);
       }
       release(nd.a);
       release(nd.b);
-      if (mov >= 0) free_slots.push_back(mov);
-      int dst = alloc();
-      emit_ins(tape_op(nd.op), dst, a, &b);
-      r.slot = dst;
+      if (spill >= 0) free_slots.push_back(spill);
+      r.w = IN_ACC;
+    }
+    if (r.w == IN_ACC && uses[k] > 1) {  // a shared node: keep a copy
+      r.slot = alloc();
+      emit_ins(A_ST, r.slot);
     }
     done[k] = 1;
     result[k] = r;
+    if (r.w == IN_ACC && r.slot >= 0) {  // later uses read the slot
+      result[k].w = IN_SLOT;
+    }
     return r;
   }
 };
@@ -155,15 +214,19 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
     } else if (is_unary(nd.op)) {
       if (nd.a < 0 || nd.a >= k) return fail(FX_E_ARG, "node %d: operand %d not earlier", k, nd.a);
       c.uses[nd.a]++;
-      c.need[k] = std::max(1, c.need[nd.a]);
+      c.need[k] = c.need[nd.a];
       c.depth[k] = c.depth[nd.a] + 1;
     } else if (is_binary(nd.op)) {
       if (nd.a < 0 || nd.a >= k || nd.b < 0 || nd.b >= k)
         return fail(FX_E_ARG, "node %d: operands %d, %d not earlier", k, nd.a, nd.b);
       c.uses[nd.a]++;
       c.uses[nd.b]++;
+      // slots needed beyond the accumulator: a computed operand is held in
+      // a slot while the other is computed, if that one needs code too
+      const bool ca = is_unary(nodes[nd.a].op) || is_binary(nodes[nd.a].op);
+      const bool cb = is_unary(nodes[nd.b].op) || is_binary(nodes[nd.b].op);
       const int na = c.need[nd.a], nb = c.need[nd.b];
-      c.need[k] = std::max(1, na == nb ? na + 1 : std::max(na, nb));
+      c.need[k] = (ca && cb) ? (na == nb ? na + 1 : std::max(na, nb)) : std::max(na, nb);
       c.depth[k] = std::max(c.depth[nd.a], c.depth[nd.b]) + 1;
     } else {
       return fail(FX_E_ARG, "node %d: unknown operator %d", k, nd.op);
@@ -175,17 +238,11 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
   c.next_slot = c.max_slot = c.n_in;
   c.prog = prog;
   operand root = c.emit(n - 1);
-  if (c.status != FX_OK) return c.status;
-  if (root.imm) {  // a constant expression
-    int dst = c.alloc();
-    c.emit_ins(T_MOV, dst, root, nullptr);
-    root.imm = false;
-    root.slot = dst;
-  }
+  if (root.w != IN_ACC) c.load(root);  // a leaf, a constant or a stored node
+  c.flush();                           // a root abs / neg
   if (c.status != FX_OK) return c.status;
   if (c.max_slot > kTapeMaxSlots)
     return fail(FX_E_UNSUPPORTED, "tape needs %d live slots (at most %d)", c.max_slot, kTapeMaxSlots);
-  prog->root = root.slot;
   prog->n_slots = c.max_slot;
   info->n_inputs = c.n_in;
   info->depth = c.depth[n - 1];
@@ -220,6 +277,18 @@ int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out) {
 }
 
 void fx_tape_destroy(fx_tape* t) { delete t; }
+
+int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, double* imm, int32_t cap) {
+  if (!t) return -fail(FX_E_ARG, "NULL tape");
+  const int32_t n = t->prog.n_ins;
+  if (cap > 0 && (!op || !slot || !imm)) return -fail(FX_E_ARG, "NULL output array");
+  for (int32_t i = 0; i < n && i < cap; ++i) {
+    op[i] = t->prog.ins[i].op;
+    slot[i] = (uint8_t)t->prog.ins[i].a;
+    imm[i] = t->prog.ins[i].kd;
+  }
+  return n;
+}
 
 int fx_tape_describe(const fx_tape* t, fx_tape_info* out) {
   if (!t || !out) return fail(FX_E_ARG, "NULL argument");

@@ -1,18 +1,24 @@
 // Run-time expression tapes.
 //
 // Expressions whose tree is only known at run time cannot be C++ types, so
-// the host compiles the tree into a short register program (three-address
-// code over at most kTapeMaxSlots slots, constants as immediates) and the
-// device interprets it per element.  The program travels inside the kernel
-// argument, so every instruction fetch is a wave-uniform scalar load.  Each
-// lane's slot file is one 16-wide vector value indexed with those uniform
-// slot numbers, which gfx950 serves from VGPRs in indexed mode
-// (s_set_gpr_idx_on) rather than from private memory; lanes are interpreted
-// in passes of 4 (FP32 compute) or 2 (FP64) so the files stay in registers.  TapeExpr<T> has the same
-// interface as a compile-time expression, so the element-wise, full
-// reduction, column-sum and row-sum skeletons (and their single-pass
-// finish) serve tapes unchanged; its eval_tile overload loads every input
-// of all EPT vectors before interpreting them one vector at a time.
+// the host compiles the tree into a short accumulator program and the device
+// interprets it per element.  The running value lives in ordinary registers
+// (the accumulator); values needed later (inputs, spilled partial results,
+// nodes used more than once) live in a slot file of at most kTapeMaxSlots
+// entries, and constants travel as immediates.  An instruction combines the
+// accumulator with at most one slot or immediate, so a chain of operators
+// such as exp(0 - abs(a)) costs only its arithmetic.  The program travels
+// inside the kernel argument (or, for batches, in device memory), so every
+// instruction fetch is a wave-uniform scalar load and the dispatch is a
+// uniform branch.  Each lane's slot file is one 16-wide vector value indexed
+// with those uniform slot numbers, which gfx950 serves from VGPRs in indexed
+// mode (s_set_gpr_idx_on) rather than from private memory; lanes are
+// interpreted in passes of 4 (FP32 compute) or 2 (FP64) so the files stay in
+// registers.  TapeExpr<T> has the same interface as a compile-time
+// expression, so the element-wise, full reduction, column-sum and row-sum
+// skeletons (and their single-pass finish) serve tapes unchanged; its
+// eval_tile overload loads every input of all EPT vectors before
+// interpreting them one vector at a time.
 #pragma once
 
 #include "fx_kernels.hpp"
@@ -22,99 +28,159 @@ namespace fx {
 constexpr int kTapeMaxIn = 4;
 constexpr int kTapeMaxIns = 128;
 constexpr int kTapeMaxSlots = 16;
-constexpr uint8_t kImm = 0xFF;
 
-enum : uint8_t { T_ADD = 0, T_SUB, T_MUL, T_DIV, T_NEG, T_ABS, T_EXP, T_SQRT, T_MOV };
+// acc is the accumulator, y the operand: slot s[a] (suffix S) or the
+// immediate (suffix I).  R-forms put the operand on the left.  The codes are
+// the fx_tape_opcode values of the C interface.
+enum : uint8_t {
+  A_LD = 0,  // acc = s[a]
+  A_LDI,     // acc = k
+  A_ST,      // s[a] = acc
+  A_ADD_S, A_ADD_I,    // acc = acc + y
+  A_SUB_S, A_SUB_I,    // acc = acc - y
+  A_RSUB_S, A_RSUB_I,  // acc = y - acc
+  A_MUL_S, A_MUL_I,    // acc = acc % y
+  A_DIV_S, A_DIV_I,    // acc = acc / y
+  A_RDIV_S, A_RDIV_I,  // acc = y / acc
+  A_NEG, A_ABS, A_EXP, A_SQRT,  // acc = f(acc)
+  A_N_OPS
+};
+static_assert(A_LD == FX_TI_LD && A_ST == FX_TI_ST && A_ADD_S == FX_TI_ADD_S &&
+                  A_RDIV_I == FX_TI_RDIV_I && A_SQRT == FX_TI_SQRT,
+              "interpreter opcodes follow fx_tape_opcode");
+// Input modifiers of an instruction that reads the accumulator: acc = |acc|
+// and then acc = -acc before the operation.  The compiler folds abs and neg
+// nodes into the next instruction this way (both are exact).
+constexpr uint16_t kAbsIn = FX_TI_ABS_IN, kNegIn = FX_TI_NEG_IN;
 
+// op and a fill the first 32-bit word together so that a fetch through a
+// device pointer (batches) stays one scalar load: a narrower field would let
+// the compiler shrink it to a 16-bit vector load, whose wait also waits for
+// every input load in flight.
 struct tape_ins {
-  uint8_t op, dst, a, b;  // a/b: slot index or kImm
-  float kf;               // immediate for FP32 compute
-  double kd;              // immediate for FP64 compute
+  uint16_t op, a;  // a: slot index (LD, ST and S-forms)
+  float kf;        // immediate for FP32 compute
+  double kd;       // immediate for FP64 compute
 };
 
+// ins[n_ins] is always readable (the array has one spare zero entry): the
+// interpreter fetches instruction pc + 1 while it executes instruction pc.
 struct tape_prog {
-  int32_t n_ins, n_in, root, n_slots;
-  tape_ins ins[kTapeMaxIns];
+  int32_t n_ins, n_in, n_slots, pad;
+  tape_ins ins[kTapeMaxIns + 1];
 };
 
 template <class C> __device__ __forceinline__ C tape_imm(const tape_ins& I);
 template <> __device__ __forceinline__ float tape_imm<float>(const tape_ins& I) { return I.kf; }
 template <> __device__ __forceinline__ double tape_imm<double>(const tape_ins& I) { return I.kd; }
 
-template <class C> struct slot_file;
-template <> struct slot_file<float> { typedef float type __attribute__((ext_vector_type(16))); };
-template <> struct slot_file<double> { typedef double type __attribute__((ext_vector_type(16))); };
-template <class C> using slots_t = typename slot_file<C>::type;
+// Slot files.  Each is one 16-wide vector value, the width for which the
+// compiler indexes registers in place (narrower vectors get select chains).
+// A program needing at most 8 slots keeps two lanes per file, interleaved
+// (element 2 * slot + lane): half the registers, higher occupancy; every
+// generated tree so far fits.  Otherwise each lane has a file of 16 slots.
+template <class C> struct slot_vec;
+template <> struct slot_vec<float> { typedef float type __attribute__((ext_vector_type(16))); };
+template <> struct slot_vec<double> { typedef double type __attribute__((ext_vector_type(16))); };
+template <class C> using slots_t = typename slot_vec<C>::type;
+constexpr int kTapeSmallSlots = 8;
+// lanes per file, files for L lanes
+template <int S> constexpr int kLanesPerFile = 16 / S;
+template <int S, int L> constexpr int kFiles = (L + kLanesPerFile<S> - 1) / kLanesPerFile<S>;
+#define FX_SLOT(f, j, a) f[(j) / P][(a) * P + (j) % P]
 template <class C> constexpr int kPassLanes = sizeof(C) == 4 ? 4 : 2;
 
-// Interpret `prog` on L lanes whose inputs already sit in slots [0, n_in).
-template <class C, int L>
-__device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[L]) {
-  for (int pc = 0; pc < prog.n_ins; ++pc) {
-    const tape_ins I = prog.ins[pc];
+// acc[j] = OP(acc[j], y) for slot and immediate operands (and the reversed
+// forms): each case computes straight into the accumulator so no operand
+// copies survive the branch merge.
+#define FX_TAPE_BIN(NAME, OPK)                                                     \
+  case A_##NAME##_S:                                                              \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], FX_SLOT(s, j, I.a)); \
+    break;                                                                        \
+  case A_##NAME##_I:                                                              \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], k); \
+    break;                                                                        \
+  case A_R##NAME##_S:                                                             \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(FX_SLOT(s, j, I.a), acc[j]); \
+    break;                                                                        \
+  case A_R##NAME##_I:                                                             \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(k, acc[j]); \
+    break;
+
+#define FX_TAPE_UN(NAME, OPK)                                                     \
+  case A_##NAME:                                                                  \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j]);    \
+    break;
+
+// Interpret `prog` on L lanes whose inputs already sit in slots [0, n_in);
+// the result is left in acc.
+template <class C, int L, int S>
+__device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[kFiles<S, L>],
+                                         C (&acc)[L]) {
+  constexpr int P = kLanesPerFile<S>;
+  const int n = prog.n_ins;
+  tape_ins I = prog.ins[0];
+  for (int pc = 0; pc < n; ++pc) {
+    const tape_ins next = prog.ins[pc + 1];
     const C k = tape_imm<C>(I);
-    C x[L], y[L];
-    if (I.a == kImm) {
+    const unsigned op = I.op;
+    if (op & (kAbsIn | kNegIn)) {
+      if (op & kAbsIn)
 #pragma unroll
-      for (int j = 0; j < L; ++j) x[j] = k;
-    } else {
+        for (int j = 0; j < L; ++j) acc[j] = op_abs::apply(acc[j]);
+      if (op & kNegIn)
 #pragma unroll
-      for (int j = 0; j < L; ++j) x[j] = s[j][I.a];
+        for (int j = 0; j < L; ++j) acc[j] = op_neg::apply(acc[j]);
     }
-    if (I.op <= T_DIV) {
-      if (I.b == kImm) {
+    switch (op & 0xFFu) {
+      case A_LD:
 #pragma unroll
-        for (int j = 0; j < L; ++j) y[j] = k;
-      } else {
-#pragma unroll
-        for (int j = 0; j < L; ++j) y[j] = s[j][I.b];
-      }
-    }
-    switch (I.op) {
-      case T_ADD:
-#pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_add::apply(x[j], y[j]);
+        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, I.a);
         break;
-      case T_SUB:
+      case A_LDI:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_sub::apply(x[j], y[j]);
+        for (int j = 0; j < L; ++j) acc[j] = k;
         break;
-      case T_MUL:
+      case A_ST:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_schur::apply(x[j], y[j]);
+        for (int j = 0; j < L; ++j) FX_SLOT(s, j, I.a) = acc[j];
         break;
-      case T_DIV:
+      case A_ADD_S:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_div::apply(x[j], y[j]);
+        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], FX_SLOT(s, j, I.a));
         break;
-      case T_NEG:
+      case A_ADD_I:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_neg::apply(x[j]);
+        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], k);
         break;
-      case T_ABS:
+      FX_TAPE_BIN(SUB, op_sub)
+      case A_MUL_S:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_abs::apply(x[j]);
+        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], FX_SLOT(s, j, I.a));
         break;
-      case T_EXP:
+      case A_MUL_I:
 #pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_exp::apply(x[j]);
+        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], k);
         break;
-      case T_SQRT:
-#pragma unroll
-        for (int j = 0; j < L; ++j) x[j] = op_sqrt::apply(x[j]);
-        break;
-      default:  // T_MOV
+      FX_TAPE_BIN(DIV, op_div)
+      FX_TAPE_UN(NEG, op_neg)
+      FX_TAPE_UN(ABS, op_abs)
+      FX_TAPE_UN(EXP, op_exp)
+      FX_TAPE_UN(SQRT, op_sqrt)
+      default:
         break;
     }
-#pragma unroll
-    for (int j = 0; j < L; ++j) s[j][I.dst] = x[j];
+    I = next;
   }
 }
+
+#undef FX_TAPE_BIN
+#undef FX_TAPE_UN
 
 // BYREF = false: the program is held by value (it travels in the kernel
 // argument); BYREF = true: it is read through a pointer into device memory
 // (the batch kernel, where each tile may run a different program).
-template <class T, bool BYREF = false> struct TapeExpr : expr_tag {
+template <class T, bool BYREF = false, int SLOTS = kTapeSmallSlots> struct TapeExpr : expr_tag {
   using storage = T;
   using ct = ct_t<T>;
   const T* p[kTapeMaxIn];
@@ -134,17 +200,21 @@ template <class T, bool BYREF = false> struct TapeExpr : expr_tag {
     lanes<ct, N> r;
 #pragma unroll
     for (int g = 0; g < N; g += G) {
-      slots_t<ct> s[G];
+      constexpr int P = kLanesPerFile<SLOTS>;
+      slots_t<ct> s[kFiles<SLOTS, G>];
 #pragma unroll
-      for (int j = 0; j < G; ++j) {
-        s[j] = slots_t<ct>{};
+      for (int f = 0; f < kFiles<SLOTS, G>; ++f) s[f] = slots_t<ct>{};
+#pragma unroll
+      for (int j = 0; j < G; ++j)
 #pragma unroll
         for (int q = 0; q < kTapeMaxIn; ++q)
-          if (q < pr.n_in) s[j][q] = in[q].v[g + j];
-      }
-      tape_run<ct, G>(pr, s);
+          if (q < pr.n_in) FX_SLOT(s, j, q) = in[q].v[g + j];
+      ct acc[G];
 #pragma unroll
-      for (int j = 0; j < G; ++j) r.v[g + j] = s[j][pr.root];
+      for (int j = 0; j < G; ++j) acc[j] = ct(0);
+      tape_run<ct, G, SLOTS>(pr, s, acc);
+#pragma unroll
+      for (int j = 0; j < G; ++j) r.v[g + j] = acc[j];
     }
     return r;
   }
@@ -170,8 +240,8 @@ template <class T, bool BYREF = false> struct TapeExpr : expr_tag {
   }
 };
 
-template <int N, int EPT, class T, bool BYREF>
-__device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF>& e, int64_t base, int64_t stride,
+template <int N, int EPT, class T, bool BYREF, int SLOTS>
+__device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF, SLOTS>& e, int64_t base, int64_t stride,
                                           lanes<ct_t<T>, N> (&r)[EPT]) {
   using C = ct_t<T>;
   lanes<C, N> in[EPT][kTapeMaxIn];
@@ -185,7 +255,7 @@ __device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF>& e, int64_t b
   for (int k = 0; k < EPT; ++k) r[k] = e.template interpret<N>(in[k]);
 }
 
-template <class T, bool B> struct max_ept<TapeExpr<T, B>> { static constexpr int value = 2; };
+template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static constexpr int value = 2; };
 
 // Evaluate a tape of storage type T (defined once per dtype, in its own
 // translation unit, to keep compile times short).
@@ -193,25 +263,33 @@ template <class T>
 int tape_eval_typed(const tape_prog& prog, const void* const* inputs, fx_shape s, int kind,
                     void* out, void* ws, size_t ws_bytes, const fx_launch* cfg, hipStream_t st);
 
+template <class T, int SLOTS>
+int tape_eval_impl(const tape_prog& prog, const void* const* inputs, fx_shape s, int kind,
+                   void* out, void* ws, size_t ws_bytes, const fx_launch* cfg, hipStream_t st) {
+  TapeExpr<T, false, SLOTS> e;
+  for (int q = 0; q < kTapeMaxIn; ++q)
+    e.p[q] = q < prog.n_in ? static_cast<const T*>(inputs[q]) : nullptr;
+  e.n_rows = s.n_rows;
+  e.n_cols = s.n_cols;
+  e.prog = prog;
+  switch (kind) {
+    case 0: return eval(static_cast<T*>(out), e, cfg, st);
+    case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, cfg, st);
+    case FX_R_NORM: return reduce_full<map_sq>(e, out, ws, ws_bytes, cfg, st);
+    case FX_R_COLSUM: case FX_R_ROWSUM:
+      return reduce_dim(kind, e, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, st);
+  }
+  return fail(FX_E_ARG, "unknown kind %d for a tape", kind);
+}
+
 #define FX_TAPE_EVAL_DEFINE(T)                                                                    \
   template <>                                                                                     \
   int tape_eval_typed<T>(const tape_prog& prog, const void* const* inputs, fx_shape s, int kind, \
                          void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,              \
                          hipStream_t st) {                                                        \
-    TapeExpr<T> e;                                                                                \
-    for (int q = 0; q < kTapeMaxIn; ++q)                                                          \
-      e.p[q] = q < prog.n_in ? static_cast<const T*>(inputs[q]) : nullptr;                       \
-    e.n_rows = s.n_rows;                                                                          \
-    e.n_cols = s.n_cols;                                                                          \
-    e.prog = prog;                                                                                \
-    switch (kind) {                                                                               \
-      case 0: return eval(static_cast<T*>(out), e, cfg, st);                                      \
-      case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, cfg, st);                 \
-      case FX_R_NORM: return reduce_full<map_sq>(e, out, ws, ws_bytes, cfg, st);                 \
-      case FX_R_COLSUM: case FX_R_ROWSUM:                                                         \
-        return reduce_dim(kind, e, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, st);      \
-    }                                                                                             \
-    return fail(FX_E_ARG, "unknown kind %d for a tape", kind);                                    \
+    if (prog.n_slots <= kTapeSmallSlots)                                                          \
+      return tape_eval_impl<T, kTapeSmallSlots>(prog, inputs, s, kind, out, ws, ws_bytes, cfg, st); \
+    return tape_eval_impl<T, kTapeMaxSlots>(prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);  \
   }
 
 // Host: compile a node list (children first, root last) into a program.

@@ -324,3 +324,38 @@ def test_empty_dimension_sums_write_zero():
     fx.fx_accu_xy(X, X, s, None)
     torch.cuda.synchronize()
     assert (cs == 0).all().item() and (rs == 0).all().item() and s.item() == 0.0
+
+
+# Arguments naming one buffer several times: the kernels read each distinct
+# (address, type) once and reuse it for every leaf naming it.
+ALIASES = {"x_y_w": (0, 1, 2), "y_is_x": (0, 0, 1), "w_is_x": (0, 1, 0), "w_is_y": (0, 1, 1),
+           "all_x": (0, 0, 0)}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("alias", list(ALIASES))
+def test_c2_repeated_buffers(dtype, alias):
+    torch, fx = need_gpu()
+    shape = (257, 129)
+    n = shape[0] * shape[1]
+    host, dev = inputs(12, n, dtype)
+    pick = ALIASES[alias]
+    hx, dx = [host[q] for q in pick], [dev[q] for q in pick]
+    e = oracle.EXPRS["c2_z"]
+    Z = empty(n, dtype)
+    fx.fx_c2_z(*dx, Z, shape)
+    acc = "f64" if dtype == "f64" else "f32"
+    cs = empty(shape[1], acc)
+    fx.fx_c2_colsum(*dx, cs, shape, fx.workspace(fx.R_COLSUM, fx.dtype_code(dx[0]), shape))
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.fx_norm_fro_diff(dx[0], dx[1], nrm, shape, fx.workspace(fx.R_NORM, fx.dtype_code(dx[0]), shape))
+    torch.cuda.synchronize()
+    out = dtype if dtype == "bf16" else None
+    v, mu = oracle.evaluate(e, hx, dtype, shape=shape)
+    assert_close(from_dev(Z, dtype), v, mu, dtype, "c2_z %s" % alias, out_dtype=out)
+    v, mu = oracle.evaluate(e, hx, dtype, shape=shape, reduce="colsum")
+    assert_close(from_dev(cs, acc), v, mu, dtype, "c2 colsum %s" % alias)
+    v, mu = oracle.evaluate(oracle.EXPRS["diff"], hx[:2], dtype, shape=shape, reduce="norm")
+    assert_close(nrm.cpu().numpy(), v, mu, dtype, "norm %s" % alias)
+    if pick[0] == pick[1]:
+        assert nrm.item() == 0.0   # X - X is exactly zero

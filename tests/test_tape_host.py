@@ -1,6 +1,10 @@
 """CPU tests of the run-time tape compiler (no kernels are launched)."""
+import numpy as np
 import pytest
 
+import oracle
+import synth
+from gpu_util import oracle_expr
 from synth import trees
 
 
@@ -19,28 +23,64 @@ def test_compile_simple(fx):
     nodes = [("leaf", -1, -1, 0, 0), ("leaf", -1, -1, 1, 0), ("mul", 0, 1, -1, 0),
              ("const", -1, -1, -1, 2.0), ("leaf", -1, -1, 2, 0), ("mul", 3, 4, -1, 0),
              ("add", 2, 5, -1, 0)]
-    info = fx.Tape(nodes).info()
+    t = fx.Tape(nodes)
+    info = t.info()
     assert info["n_inputs"] == 3 and info["depth"] == 2
-    assert info["n_instructions"] == 3          # the constant is an immediate
     assert info["op_count"][:4] == [1, 0, 2, 0] and info["n_consts"] == 1
-    assert info["n_slots"] <= 5
+    # X % Y into the accumulator, kept in slot 3 while 2 * W is computed
+    # (the constant is an immediate), then the sum
+    assert t.program() == [("LD", 0, 0.0), ("MUL_S", 1, 0.0), ("ST", 3, 0.0),
+                           ("LD", 2, 0.0), ("MUL_I", 0, 2.0), ("ADD_S", 3, 0.0)]
+    assert info["n_instructions"] == 6 and info["n_slots"] == 4
 
 
 def test_constant_and_leaf_trees(fx):
-    assert fx.Tape([("const", -1, -1, -1, 3.0)]).info()["n_instructions"] == 1
-    leaf = fx.Tape([("leaf", -1, -1, 0, 0)]).info()
-    assert leaf["n_instructions"] == 0 and leaf["n_inputs"] == 1
+    assert fx.Tape([("const", -1, -1, -1, 3.0)]).program() == [("LDI", 0, 3.0)]
+    leaf = fx.Tape([("leaf", -1, -1, 0, 0)])
+    assert leaf.program() == [("LD", 0, 0.0)] and leaf.info()["n_inputs"] == 1
     two = fx.Tape([("const", -1, -1, -1, 1.0), ("const", -1, -1, -1, 2.0),
-                   ("add", 0, 1, -1, 0)]).info()
-    assert two["n_instructions"] == 2           # one immediate materialised
+                   ("sub", 0, 1, -1, 0)])
+    assert two.program() == [("LDI", 0, 1.0), ("SUB_I", 0, 2.0)]
+    # an immediate on the left of a slot: the reversed form keeps the order
+    rev = fx.Tape([("const", -1, -1, -1, 1.0), ("leaf", -1, -1, 0, 0), ("div", 0, 1, -1, 0)])
+    assert rev.program() == [("LD", 0, 0.0), ("RDIV_I", 0, 1.0)]
+
+
+def test_abs_and_neg_fold_into_the_consumer(fx):
+    X = ("leaf", -1, -1, 0, 0.0)
+    # the generator's guards: sqrt(|x|), exp(0 - |x|), x / (1 + |y|)
+    t = fx.Tape([X, ("abs", 0, -1, -1, 0), ("sqrt", 1, -1, -1, 0)])
+    assert t.program() == [("LD", 0, 0.0), ("SQRT|abs", 0, 0.0)]
+    t = fx.Tape([X, ("const", -1, -1, -1, 0.0), ("abs", 0, -1, -1, 0), ("sub", 1, 2, -1, 0),
+                 ("exp", 3, -1, -1, 0)])
+    assert t.program() == [("LD", 0, 0.0), ("RSUB_I|abs", 0, 0.0), ("EXP", 0, 0.0)]
+    t = fx.Tape([X, ("leaf", -1, -1, 1, 0.0), ("const", -1, -1, -1, 1.0), ("abs", 1, -1, -1, 0),
+                 ("add", 2, 3, -1, 0), ("div", 0, 4, -1, 0)])
+    assert t.program() == [("LD", 1, 0.0), ("ADD_I|abs", 0, 1.0), ("RDIV_S", 0, 0.0)]
+    # compositions: -(-x) vanishes, -|x| keeps both, |-x| is |x|; a root
+    # modifier becomes an instruction of its own
+    nn = fx.Tape([X, ("neg", 0, -1, -1, 0), ("neg", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
+    assert nn.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0)]
+    na = fx.Tape([X, ("abs", 0, -1, -1, 0), ("neg", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
+    assert na.program() == [("LD", 0, 0.0), ("EXP|abs|neg", 0, 0.0)]
+    an = fx.Tape([X, ("neg", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
+    assert an.program() == [("LD", 0, 0.0), ("EXP|abs", 0, 0.0)]
+    root = fx.Tape([X, ("exp", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("neg", 2, -1, -1, 0)])
+    assert root.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0), ("ABS", 0, 0.0), ("NEG", 0, 0.0)]
+    # a shared abs node is stored with its modifier applied
+    sh = fx.Tape([X, ("exp", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("mul", 2, 2, -1, 0)])
+    assert sh.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0), ("ST|abs", 1, 0.0), ("MUL_S", 1, 0.0)]
 
 
 def test_dag_shared_node(fx):
     # t = X + Y used twice: (t % t) - t
     nodes = [("leaf", -1, -1, 0, 0), ("leaf", -1, -1, 1, 0), ("add", 0, 1, -1, 0),
              ("mul", 2, 2, -1, 0), ("sub", 3, 2, -1, 0)]
-    info = fx.Tape(nodes).info()
-    assert info["n_instructions"] == 3 and info["op_count"][:3] == [1, 1, 1]
+    t = fx.Tape(nodes)
+    assert t.info()["op_count"][:3] == [1, 1, 1]
+    # t is computed once and kept in a slot for its later uses
+    assert t.program() == [("LD", 0, 0.0), ("ADD_S", 1, 0.0), ("ST", 2, 0.0),
+                           ("MUL_S", 2, 0.0), ("SUB_S", 2, 0.0)]
 
 
 @pytest.mark.parametrize("bad", [
@@ -92,3 +132,67 @@ def test_tree_generator_is_deterministic():
     s = trees.batch_set(64)
     assert all(256 <= t["n"] <= 1 << 20 for t in s)
     assert sum(1 for t in s if t["reduce"] == "accu") == 32
+
+
+def run_program(prog, inputs):
+    """Execute an accumulator program in FP64 with numpy (the machine that
+    fx_tape_program documents)."""
+    slots = [None] * 16
+    for q, x in enumerate(inputs):
+        slots[q] = x.astype(np.float64)
+    acc = None
+    for name, s, k in prog:
+        op, *mods = name.split("|")
+        if "abs" in mods:
+            acc = np.abs(acc)
+        if "neg" in mods:
+            acc = -acc
+        y = slots[s] if op.endswith("_S") or op == "LD" else k
+        if op == "LD":
+            acc = slots[s].copy()
+        elif op == "LDI":
+            acc = np.full(inputs[0].shape if inputs else (1,), k)
+        elif op == "ST":
+            slots[s] = acc.copy()
+        elif op.startswith("ADD"):
+            acc = acc + y
+        elif op.startswith("SUB"):
+            acc = acc - y
+        elif op.startswith("RSUB"):
+            acc = y - acc
+        elif op.startswith("MUL"):
+            acc = acc * y
+        elif op.startswith("DIV"):
+            acc = acc / y
+        elif op.startswith("RDIV"):
+            acc = y / acc
+        elif op == "NEG":
+            acc = -acc
+        elif op == "ABS":
+            acc = np.abs(acc)
+        elif op == "EXP":
+            acc = np.exp(acc)
+        else:
+            acc = np.sqrt(acc)
+    return acc
+
+
+@pytest.mark.parametrize("which", ["batch", "tuning"])
+def test_programs_compute_the_tree(fx, which):
+    """Every generated tree's program, run in FP64 on the host, agrees with
+    the oracle's node-by-node FP64 evaluation: operand order, reversed forms,
+    spills and slot reuse all show up here."""
+    n = 257
+    for i in range(250):
+        if which == "batch":
+            nodes, k, _ = trees.random_tree(4, i)
+        else:
+            nodes = trees.tuning_item(5, i)["nodes"]
+            k = max([nd[3] for nd in nodes if nd[0] == "leaf"] + [-1]) + 1
+        xs = [synth.fill_f64(11, t, n) for t in range(k)]
+        got = run_program(fx.Tape(nodes).program(), xs)
+        v, mu = oracle.evaluate(oracle_expr(nodes), xs, "f64") if k else (None, None)
+        if k == 0:
+            continue
+        ok, rep = oracle.check(got, v, mu, "f64")
+        assert ok.all(), (which, i, rep)
