@@ -59,6 +59,10 @@ def lib():
         L.or_eval.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, P,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                               ctypes.c_double, ctypes.c_double, P, P]
+        L.or_eval_views.restype = ctypes.c_int
+        L.or_eval_views.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, P,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, P, P, P, P, P]
         L.or_eval_u32.restype = ctypes.c_int
         L.or_eval_u32.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P,
                                   ctypes.c_int64, P, P]
@@ -78,10 +82,13 @@ def num_threads() -> int:
 class E:
     """A node of an expression tree."""
 
-    __slots__ = ("op", "kids", "leaf", "cst")
+    __slots__ = ("op", "kids", "leaf", "cst", "view")
 
-    def __init__(self, op, kids=(), leaf=-1, cst=0.0):
+    def __init__(self, op, kids=(), leaf=-1, cst=0.0, view=None):
         self.op, self.kids, self.leaf, self.cst = op, tuple(kids), leaf, cst
+        # leaves only: None (dense), "T" (transposed dense), or (off, rs, cs):
+        # element (r, c) of the view is input[off + r*rs + c*cs]
+        self.view = view
 
     @staticmethod
     def wrap(v):
@@ -102,6 +109,26 @@ class E:
     def __rtruediv__(self, o): return E("div", (E.wrap(o), self))
     def __neg__(self): return E("neg", (self,))
     def __xor__(self, o): return E("xor", (self, E.wrap(o)))
+
+    def t(self):
+        """The transpose (Sec. 3): element (r, c) of E.t() is E(c, r), so every
+        leaf's access swaps row and column; a double transpose cancels."""
+        memo = {}
+
+        def tr(e):
+            if id(e) in memo:
+                return memo[id(e)]
+            if e.op == "leaf":
+                v = e.view
+                nv = "T" if v is None else None if v == "T" else (v[0], v[2], v[1])
+                r = E("leaf", leaf=e.leaf, view=nv)
+            elif e.op == "const":
+                r = e
+            else:
+                r = E(e.op, tuple(tr(k) for k in e.kids), e.leaf, e.cst)
+            memo[id(e)] = r
+            return r
+        return tr(self)
 
     def nodes(self):
         """Post-order list of distinct nodes (root last)."""
@@ -136,6 +163,18 @@ class E:
 
 def leaf(i: int) -> E:
     return E("leaf", leaf=i)
+
+
+def submat(i: int, r0: int, c0: int, ld: int) -> E:
+    """Input i (column-major, leading dimension ld) from row r0, column c0:
+    the submatrix view (its size is the expression's shape)."""
+    return E("leaf", leaf=i, view=(r0 + c0 * ld, 1, ld))
+
+
+def diag(i: int, k: int, ld: int) -> E:
+    """Diagonal k of input i (leading dimension ld) as a column vector:
+    element j is X(j + max(-k, 0), j + max(k, 0))."""
+    return E("leaf", leaf=i, view=(max(-k, 0) + max(k, 0) * ld, ld + 1, 0))
 
 
 def const(c: float) -> E:
@@ -195,6 +234,41 @@ def paper_expr(name: str, beta: float = 1.0, alpha: float = 0.044715) -> E:
     raise KeyError(name)
 
 
+def center(m: int, n: int):
+    """The centre submatrix with half the rows and columns of an m x n
+    matrix (Sec. 4): (r0, c0, rows, cols)."""
+    R, C = m // 2, n // 2
+    return (m - R) // 2, (n - C) // 2, R, C
+
+
+def diag_len(m: int, n: int, k: int) -> int:
+    return max(0, min(m, n - k) if k >= 0 else min(m + k, n))
+
+
+# The paper's expressions with strided views (Sec. 4) over m x n inputs
+# (column-major, leading dimension m).  Returns (expression, result shape).
+def paper_view_expr(name: str, m: int, n: int, a: float = 2.0):
+    if name in ("addsub2", "addsub4"):
+        r0, c0, R, C = center(m, n)
+        k = 2 if name == "addsub2" else 4
+        e = submat(0, r0, c0, m)
+        for q in range(1, k):
+            e = e + submat(q, r0, c0, m)
+        return e, (R, C)
+    if name == "expr1":                      # Z = 2 * (X.t() + Y) + 2 * (X + Y.t())
+        assert m == n
+        X, Y = leaf(0), leaf(1)
+        return 2 * (X.t() + Y) + 2 * (X + Y.t()), (m, n)
+    if name == "expr2":                      # Z = a * A + (B + C).t() + log(pow(D, 2))
+        assert m == n
+        A, B, C, D = leaf(0), leaf(1), leaf(2), leaf(3)
+        return a * A + (B + C).t() + log(pow_(D, 2)), (m, n)
+    if name == "diagsum":                    # (X.diag(-1) + X.diag(1)) % (Y.diag(-1) + Y.diag(1))
+        L = min(diag_len(m, n, -1), diag_len(m, n, 1))
+        return ((diag(0, -1, m) + diag(0, 1, m)) % (diag(1, -1, m) + diag(1, 1, m))), (L, 1)
+    raise KeyError(name)
+
+
 def axy_expw(a: float) -> E:
     """Z = a*X % Y + exp(-W) for a run-time scalar a (the scalar is held in
     the compute type by the caller, so pass it already rounded)."""
@@ -229,8 +303,13 @@ def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
     if shape is None:
         shape = (n, 1)
     rows, cols = shape
-    assert all(x.size == rows * cols for x in inputs)
     assert expr.n_inputs() <= len(inputs)
+    order, _ = expr.nodes()
+    views = any(e.op == "leaf" and e.view is not None for e in order)
+    if views:
+        voff, vrs, vcs = _views(order, inputs, rows, cols)
+    else:
+        assert all(x.size == rows * cols for x in inputs)
     if u_c is None:
         u_c = compute_unit(dtype)
     op, a, b, lf, cst = expr.arrays()
@@ -240,13 +319,41 @@ def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
     mu = np.empty(max(nout, 1), np.float64)
     dts = np.array([DTYPE[d] for d in (input_dtypes or [dtype] * len(inputs))] or [0],
                    dtype=np.int32)
-    rc = lib().or_eval(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
-                       lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
-                       dts.ctypes.data, rows, cols, red, u_c, fexp, out.ctypes.data,
-                       mu.ctypes.data)
+    if views:
+        rc = lib().or_eval_views(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
+                                 lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
+                                 dts.ctypes.data, rows, cols, red, u_c, fexp, voff.ctypes.data,
+                                 vrs.ctypes.data, vcs.ctypes.data, out.ctypes.data,
+                                 mu.ctypes.data)
+    else:
+        rc = lib().or_eval(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
+                           lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
+                           dts.ctypes.data, rows, cols, red, u_c, fexp, out.ctypes.data,
+                           mu.ctypes.data)
     if rc != 0:
         raise ValueError("oracle evaluation failed (%d)" % rc)
     return out[:nout], mu[:nout]
+
+
+def _views(order, inputs, rows, cols):
+    """Per-node (off, rs, cs) arrays for an expression of shape rows x cols;
+    every view must stay inside its input."""
+    voff = np.zeros(len(order), np.int64)
+    vrs = np.ones(len(order), np.int64)
+    vcs = np.full(len(order), rows, np.int64)
+    for k, e in enumerate(order):
+        if e.op != "leaf":
+            continue
+        v = e.view
+        if v is None:
+            v = (0, 1, rows)          # dense rows x cols
+        elif v == "T":
+            v = (0, cols, 1)          # the transpose of a dense cols x rows input
+        voff[k], vrs[k], vcs[k] = v
+        if rows * cols:
+            idx = [v[0] + r * v[1] + c * v[2] for r in (0, rows - 1) for c in (0, cols - 1)]
+            assert 0 <= min(idx) and max(idx) < inputs[e.leaf].size, "view outside its input"
+    return voff, vrs, vcs
 
 
 def evaluate_u32(expr: E, inputs):

@@ -148,11 +148,23 @@ static int const_exact(double c, double u_c) {
 
 /* Node arrays: op, a, b (child node indices, earlier than the node), leaf
  * (input index for OR_LEAF), cst (value for OR_CONST). */
+/* A leaf's view of its input (NULL arrays: every leaf dense).  Element
+ * (r, c) of the view is input[off + r * rs + c * cs]; a dense leaf of an
+ * n_rows x n_cols expression is off = 0, rs = 1, cs = n_rows.  Transposes,
+ * submatrices and diagonals are all of this form (Sec. 3: the transposed
+ * access swaps row and column in the index). */
+typedef struct {
+  const int64_t* off;
+  const int64_t* rs;
+  const int64_t* cs;
+  int64_t n_rows;
+} views_t;
+
 static void eval_node(int k, const int32_t* op, const int32_t* ca,
                       const int32_t* cb, const int32_t* leaf, const double* cst,
                       const void* const* inputs, const int* dtypes, int64_t e0,
                       int64_t len, double** V, double** M, double u_c,
-                      double fexp) {
+                      double fexp, const views_t* vw) {
   double* v = V[k];
   double* m = M[k];
   const double* va = ca[k] >= 0 ? V[ca[k]] : NULL;
@@ -164,8 +176,18 @@ static void eval_node(int k, const int32_t* op, const int32_t* ca,
     case OR_LEAF: {
       const void* p = inputs[leaf[k]];
       const int dt = dtypes[leaf[k]];
+      if (vw->off) {
+        const int64_t off = vw->off[k], rs = vw->rs[k], cs = vw->cs[k], R = vw->n_rows;
 #pragma omp parallel for schedule(static)
-      for (i = 0; i < len; ++i) { v[i] = widen(dt, p, e0 + i); m[i] = 0.0; }
+        for (i = 0; i < len; ++i) {
+          const int64_t r = (e0 + i) % R, c = (e0 + i) / R;
+          v[i] = widen(dt, p, off + r * rs + c * cs);
+          m[i] = 0.0;
+        }
+      } else {
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < len; ++i) { v[i] = widen(dt, p, e0 + i); m[i] = 0.0; }
+      }
       break;
     }
     case OR_CONST: {
@@ -289,11 +311,31 @@ static int check_tree(int n_nodes, const int32_t* op, const int32_t* a,
  * u_c: unit roundoff of the compute type the bound mu refers to.
  * fexp: mu allowance for exp (2 = one ulp).
  */
+int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
+                  const int32_t* leaf, const double* cst, int n_inputs,
+                  const void* const* inputs, const int* dtypes, int64_t n_rows,
+                  int64_t n_cols, int reduce, double u_c, double fexp,
+                  const int64_t* voff, const int64_t* vrs, const int64_t* vcs,
+                  double* out, double* mu);
+
 int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
             const int32_t* leaf, const double* cst, int n_inputs,
             const void* const* inputs, const int* dtypes, int64_t n_rows,
             int64_t n_cols, int reduce, double u_c, double fexp, double* out,
             double* mu) {
+  return or_eval_views(n_nodes, op, a, b, leaf, cst, n_inputs, inputs, dtypes, n_rows, n_cols,
+                       reduce, u_c, fexp, NULL, NULL, NULL, out, mu);
+}
+
+/* or_eval with a view per node (voff/vrs/vcs indexed by node; only leaves
+ * read them).  The caller keeps every view inside its input array. */
+int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
+                  const int32_t* leaf, const double* cst, int n_inputs,
+                  const void* const* inputs, const int* dtypes, int64_t n_rows,
+                  int64_t n_cols, int reduce, double u_c, double fexp,
+                  const int64_t* voff, const int64_t* vrs, const int64_t* vcs,
+                  double* out, double* mu) {
+  const views_t vw = {voff, vrs, vcs, n_rows > 0 ? n_rows : 1};
   for (int q = 0; q < n_inputs; ++q)
     if (dtypes[q] < 0 || dtypes[q] > OR_U32) return OR_EBAD;
   if (n_rows < 0 || n_cols < 0 || reduce < OR_NONE || reduce > OR_NORM) return OR_EBAD;
@@ -320,7 +362,7 @@ int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
   for (int64_t e0 = 0; e0 < n; e0 += chunk) {
     const int64_t len = (n - e0) < chunk ? (n - e0) : chunk;
     for (int k = 0; k < n_nodes; ++k)
-      eval_node(k, op, a, b, leaf, cst, inputs, dtypes, e0, len, V, M, u_c, fexp);
+      eval_node(k, op, a, b, leaf, cst, inputs, dtypes, e0, len, V, M, u_c, fexp, &vw);
     const double* v = V[root];
     const double* m = M[root];
     if (reduce == OR_NONE) {

@@ -356,3 +356,67 @@ def test_addn_is_left_to_right_sum(k):
     for t in xs[1:]:
         s32 = (s32 + t).astype(np.float32)
     assert oracle.check(s32, v, mu, "f32")[0].all()
+
+
+# ---- strided views: transpose, submatrix, diagonal (Sec. 3, Sec. 4) -----------
+
+def _mat(seed, t, m, n):
+    return synth.fill(seed, t, m * n, "f64").reshape(m, n, order="F")
+
+
+def test_views_match_numpy_indexing():
+    m, n = 7, 5
+    A = _mat(3, 0, m, n)
+    flat = [A.reshape(-1, order="F")]
+    v, _ = oracle.evaluate(X.t(), flat, "f64", shape=(n, m))          # transpose
+    assert np.array_equal(v, A.T.reshape(-1, order="F"))
+    v, _ = oracle.evaluate(X.t().t(), flat, "f64", shape=(m, n))      # double transpose
+    assert np.array_equal(v, flat[0])
+    v, _ = oracle.evaluate(oracle.submat(0, 2, 1, m), flat, "f64", shape=(3, 2))
+    assert np.array_equal(v, A[2:5, 1:3].reshape(-1, order="F"))
+    for k in (-2, -1, 0, 1, 3):
+        L = oracle.diag_len(m, n, k)
+        v, _ = oracle.evaluate(oracle.diag(0, k, m), flat, "f64", shape=(L, 1))
+        assert np.array_equal(v, np.diag(A, k)), k
+    r0, c0, R, C = oracle.center(10, 8)
+    assert (r0, c0, R, C) == (2, 2, 5, 4) and oracle.center(10000, 10000) == (2500, 2500, 5000, 5000)
+    with pytest.raises(AssertionError):          # a view outside its input is refused
+        oracle.evaluate(oracle.submat(0, 5, 4, m), flat, "f64", shape=(3, 2))
+
+
+def test_transpose_of_an_expression_moves_to_its_leaves():
+    m = 6
+    B, C = _mat(4, 1, m, m), _mat(4, 2, m, m)
+    ins = [B.reshape(-1, order="F"), C.reshape(-1, order="F")]
+    v, _ = oracle.evaluate((X + Y).t(), ins, "f64", shape=(m, m))
+    assert np.array_equal(v, (B + C).T.reshape(-1, order="F"))
+    v, _ = oracle.evaluate((X.t() - Y).t(), ins, "f64", shape=(m, m))   # (X' - Y)' = X - Y'
+    assert np.array_equal(v, (B - C.T).reshape(-1, order="F"))
+
+
+def test_paper_view_expressions():
+    m = 9
+    P = oracle.paper_view_expr
+    mats = [_mat(5, t, m, m) for t in range(4)]
+    ins = [M.reshape(-1, order="F") for M in mats]
+    e, shape = P("expr1", m, m)                 # symmetric: Z' = Z exactly
+    v, _ = oracle.evaluate(e, ins[:2], "f64", shape=shape)
+    Z = v.reshape(m, m, order="F")
+    assert np.array_equal(Z, Z.T)
+    assert np.allclose(Z, 2 * (mats[0].T + mats[1]) + 2 * (mats[0] + mats[1].T), rtol=1e-15)
+    e, shape = P("expr2", m, m, a=0.5)
+    v, _ = oracle.evaluate(e, ins, "f64", shape=shape)
+    want = 0.5 * mats[0] + (mats[1] + mats[2]).T + np.log(mats[3] ** 2)
+    assert np.allclose(v, want.reshape(-1, order="F"), rtol=1e-14)
+    for name, k in (("addsub2", 2), ("addsub4", 4)):
+        e, shape = P(name, m, m)
+        r0, c0, R, C = oracle.center(m, m)
+        v, _ = oracle.evaluate(e, ins[:k], "f64", shape=shape)
+        sub = sum(M[r0:r0 + R, c0:c0 + C] for M in mats[:k])
+        assert shape == (R, C) and np.allclose(v, sub.reshape(-1, order="F"), rtol=1e-15)
+    e, shape = P("diagsum", m, m)
+    v, _ = oracle.evaluate(e, ins[:2], "f64", shape=shape)
+    d = lambda M: np.diag(M, -1) + np.diag(M, 1)
+    assert shape == (m - 1, 1) and np.array_equal(v, d(mats[0]) * d(mats[1]))
+    v, _ = oracle.evaluate(e, [ins[0], ins[0]], "f64", shape=shape)     # X = Y: a square
+    assert np.all(v >= 0)
