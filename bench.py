@@ -248,7 +248,8 @@ def paper_suite_detail(fx, torch, stream, reps):
 
 PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
-                  for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp")]
+                  for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp", "fx_fused_c2.hip",
+                            "fx_fused_c2sum.hip", "fx_fused_xy.hip")]
 
 
 def measured_traffic(kernel_tag="k_ew[c2,f32"):

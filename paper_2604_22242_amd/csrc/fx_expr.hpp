@@ -342,6 +342,10 @@ template <class T, int K> struct SumN : expr_tag {
 // leaf k), the repeats are copied register to register, and at_regs()
 // evaluates the tree from those registers.  Leaf indices are fixed at
 // compile time by the traversal, so no register is indexed at run time.
+// The loads sit behind uniform branches, which makes the compiler wait for
+// all of them before any arithmetic; the drivers therefore take Fused<E>
+// only when some leaf does repeat, and the plain kernel (whose waits follow
+// the loads one by one) otherwise.
 constexpr int kMaxFusedLeaves = 16;
 
 template <class E, class = void> struct leaves_of { static constexpr int value = 0; };
@@ -375,6 +379,11 @@ template <class E> struct Fused : expr_tag {
     return e.template at_regs<0, N, NT>(regs, i);
   }
   void collect(leaf_info& li) const { e.collect(li); }
+  bool has_alias() const {
+    for (int k = 0; k < L; ++k)
+      if (alias[k] != k) return true;
+    return false;
+  }
 };
 
 // Host: wrap E when it has two or more register leaves.

@@ -49,58 +49,4 @@ int fx_dot(fx_dtype dt, const void* X, const void* Y, int64_t n, void* d_out, vo
   return fx_accu_xy(dt, X, Y, n, d_out, ws, ws_bytes, cfg, stream);
 }
 
-int fx_c2_z(fx_dtype dt, const void* X, const void* Y, const void* W, void* Z, fx_shape s,
-            const fx_launch* cfg, void* stream) {
-  if (int rc = check_shape(s)) return rc;
-  return with_fp(dt, [&](auto t) {
-    using T = typename decltype(t)::type;
-    auto x = leaf<T>(X, s.n_rows, s.n_cols), y = leaf<T>(Y, s.n_rows, s.n_cols),
-         w = leaf<T>(W, s.n_rows, s.n_cols);
-    return eval(static_cast<T*>(Z), (x + y) % exp(-abs(w)) / (1 + x % x), cfg, S(stream));
-  });
-}
-
-static int c2_dimsum(int kind, fx_dtype dt, const void* X, const void* Y, const void* W, void* out,
-                     fx_shape s, void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream) {
-  if (int rc = check_shape(s)) return rc;
-  return with_fp(dt, [&](auto t) {
-    using T = typename decltype(t)::type;
-    auto x = leaf<T>(X, s.n_rows, s.n_cols), y = leaf<T>(Y, s.n_rows, s.n_cols),
-         w = leaf<T>(W, s.n_rows, s.n_cols);
-    return reduce_dim(kind, (x + y) % exp(-abs(w)) / (1 + x % x),
-                      static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, S(stream));
-  });
-}
-
-int fx_c2_colsum(fx_dtype dt, const void* X, const void* Y, const void* W, void* out, fx_shape s,
-                 void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream) {
-  return c2_dimsum(FX_R_COLSUM, dt, X, Y, W, out, s, ws, ws_bytes, cfg, stream);
-}
-
-int fx_c2_rowsum(fx_dtype dt, const void* X, const void* Y, const void* W, void* out, fx_shape s,
-                 void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream) {
-  return c2_dimsum(FX_R_ROWSUM, dt, X, Y, W, out, s, ws, ws_bytes, cfg, stream);
-}
-
-int fx_norm_fro_diff(fx_dtype dt, const void* X, const void* Y, fx_shape s, double* d_out,
-                     void* ws, size_t ws_bytes, const fx_launch* cfg, void* stream) {
-  if (int rc = check_shape(s)) return rc;
-  return with_fp(dt, [&](auto t) {
-    using T = typename decltype(t)::type;
-    auto x = leaf<T>(X, s.n_rows, s.n_cols), y = leaf<T>(Y, s.n_rows, s.n_cols);
-    return reduce_full<map_sq>(x - y, d_out, ws, ws_bytes, cfg, S(stream));
-  });
-}
-
-int fx_colsum_xy(fx_dtype dt, const void* X, const void* Y, void* out, fx_shape s, void* ws,
-                 size_t ws_bytes, const fx_launch* cfg, void* stream) {
-  if (int rc = check_shape(s)) return rc;
-  return with_fp(dt, [&](auto t) {
-    using T = typename decltype(t)::type;
-    auto x = leaf<T>(X, s.n_rows, s.n_cols), y = leaf<T>(Y, s.n_rows, s.n_cols);
-    return reduce_dim(FX_R_COLSUM, x % y, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg,
-                      S(stream));
-  });
-}
-
 }  // extern "C"

@@ -360,7 +360,11 @@ template <class E, class T>
 int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st);
 template <class E, class T>
 int eval(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
-  return eval_direct(z, fuse_leaves(e), cfg, st);
+  if constexpr (leaves_of<E>::value >= 2 && leaves_of<E>::value <= kMaxFusedLeaves) {
+    const auto f = fuse_leaves(e);
+    if (f.has_alias()) return eval_direct(z, f, cfg, st);
+  }
+  return eval_direct(z, e, cfg, st);
 }
 template <class E, class T>
 int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
@@ -396,7 +400,11 @@ int reduce_full_direct(const E& e, void* out, void* ws, size_t ws_bytes, const f
 template <class M, class E>
 int reduce_full(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
                 hipStream_t st) {
-  return reduce_full_direct<M>(fuse_leaves(e), out, ws, ws_bytes, cfg, st);
+  if constexpr (leaves_of<E>::value >= 2 && leaves_of<E>::value <= kMaxFusedLeaves) {
+    const auto f = fuse_leaves(e);
+    if (f.has_alias()) return reduce_full_direct<M>(f, out, ws, ws_bytes, cfg, st);
+  }
+  return reduce_full_direct<M>(e, out, ws, ws_bytes, cfg, st);
 }
 template <class M, class E>
 int reduce_full_direct(const E& e, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
@@ -433,7 +441,11 @@ int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
 template <class O, class E>
 int reduce_dim(int kind, const E& e, O* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
                hipStream_t st) {
-  return reduce_dim_direct(kind, fuse_leaves(e), out, ws, ws_bytes, cfg, st);
+  if constexpr (leaves_of<E>::value >= 2 && leaves_of<E>::value <= kMaxFusedLeaves) {
+    const auto f = fuse_leaves(e);
+    if (f.has_alias()) return reduce_dim_direct(kind, f, out, ws, ws_bytes, cfg, st);
+  }
+  return reduce_dim_direct(kind, e, out, ws, ws_bytes, cfg, st);
 }
 template <class O, class E>
 int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
