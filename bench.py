@@ -150,6 +150,39 @@ def event_ms(torch, stream, fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def c1_detail(fx, torch, stream, reps):
+    """The small vector workload, n = 2^20 FP32 (16 MiB: it fits the 256 MB
+    last-level cache): Z = X%Y + 2W and accu(X%Y), warm (back-to-back
+    launches) and cold (a 512 MiB write between launches, outside the
+    timed events)."""
+    import synth
+    n = 1 << 20
+    X, Y, W = [torch.from_numpy(synth.fill(1, t, n, "f32")).cuda() for t in range(3)]
+    Z = torch.empty(n, device="cuda")
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = fx.workspace(fx.R_ACCU, fx.F32, (n, 1))
+    flush = torch.empty(128 << 20, device="cuda")
+    runs = {"z": (lambda: fx.fx_c1_z(X, Y, W, Z, stream=stream), 16 * n),
+            "accu": (lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), 8 * n)}
+    out = {}
+    with torch.cuda.stream(stream):
+        for name, (fn, nbytes) in runs.items():
+            warm = event_ms(torch, stream, fn, reps)
+            times = []
+            for _ in range(reps):
+                flush.fill_(1.0)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b))
+            cold = sum(times) / len(times)
+            out[name] = {"warm_us": round(warm * 1e3, 2), "warm_GB/s": round(nbytes / warm / 1e6, 1),
+                         "cold_us": round(cold * 1e3, 2), "cold_GB/s": round(nbytes / cold / 1e6, 1)}
+    return out
+
+
 def precision_detail(fx, torch, stream, reps):
     """The C1 expressions at 2^28 elements: BF16 and FP16 storage against the
     FP32 storage reference (Z = X%Y + 2W and accu(X%Y))."""
@@ -246,6 +279,35 @@ def paper_suite_detail(fx, torch, stream, reps):
     return {"expressions_10k": suite, "add_N_sweep_10k": sweep}
 
 
+def paper_views_detail(fx, torch, stream, reps):
+    """The paper's strided-view expressions at its size, 10k x 10k FP32
+    inputs (Sec. 4): centre-submatrix sums, expressions with transposes and
+    the diagonal sum; effective GB/s over the algorithmic bytes (each
+    distinct input once, plus the output)."""
+    import synth
+    m = 10000
+    n = m * m
+    ins = [torch.from_numpy(synth.fill(11, t, n, "f32")).cuda() for t in range(3)]
+    ins.append(torch.from_numpy(synth.fill(11, 3, n, "f32", "uniform12")).cuda())
+    out = {}
+    for name, k in (("addsub2", 2), ("addsub4", 4), ("expr1", 2), ("expr2", 4), ("diagsum", 2)):
+        shape = fx.fx_paper_view_shape(name, (m, m))
+        nz = shape[0] * shape[1]
+        Z = torch.empty(nz, device="cuda")
+        ms = event_ms(torch, stream, lambda: fx.fx_paper_view_expr(name, ins[:k], Z, (m, m), (1.5,),
+                                                                    stream=stream), reps)
+        if name.startswith("addsub"):
+            nbytes = (k + 1) * 4 * nz                 # k centre blocks read, Z written
+        elif name == "diagsum":
+            nbytes = 4 * 4 * (m - 1) + 4 * nz         # four diagonals read, Z written
+        else:
+            nbytes = (k + 1) * 4 * n                  # each matrix once, Z written
+        out[name] = {"ms": round(ms, 4), "GB/s": round(nbytes / ms / 1e6, 1),
+                     "out_shape": list(shape)}
+        del Z
+    return out
+
+
 PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
                   for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp", "fx_fused_c2.hip",
@@ -273,12 +335,16 @@ def measured_traffic(kernel_tag="k_ew[c2,f32"):
     return None
 
 
-def cpu_baseline(cols_sample=COLS, min_seconds=10.0):
+def cpu_baseline(cols_sample=COLS, min_seconds=10.0, threads=None):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same three results over the first `cols_sample` columns, repeated until
-    at least `min_seconds` of CPU work has been timed."""
+    at least `min_seconds` of CPU work has been timed.  threads: OpenMP
+    threads (default: all the host offers)."""
     import oracle
     import synth
+    all_threads = oracle.num_threads()
+    if threads:
+        oracle.set_threads(threads)
     n = ROWS * cols_sample
     host = [synth.fill(2, t, n, "f32") for t in range(3)]
     shape = (ROWS, cols_sample)
@@ -293,7 +359,9 @@ def cpu_baseline(cols_sample=COLS, min_seconds=10.0):
         if dt >= min_seconds:
             break
     nbytes = reps * (16 * n + 12 * n + 8 * n)
-    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+    used = oracle.num_threads()
+    oracle.set_threads(all_threads)
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": used,
             "kind": "oracle",
             "sample": "C2 FP32 Z, sum(Z,0), norm_fro(X-Y) over 8192 x %d columns, %d repetitions "
                       "in %.1f s (FP64, explicit temporaries)" % (cols_sample, reps, dt)}
@@ -361,6 +429,11 @@ def main():
         log("bench: the paper's expressions and add-N sweep, 10k x 10k")
         detail["paper_suite"] = paper_suite_detail(fx, torch, stream, 10)
         torch.cuda.empty_cache()
+        log("bench: n = 2^20 vectors, warm and cold")
+        detail["c1_2^20"] = c1_detail(fx, torch, stream, 50)
+        log("bench: the paper's strided-view expressions, 10k x 10k")
+        detail["paper_views"] = paper_views_detail(fx, torch, stream, 10)
+        torch.cuda.empty_cache()
         log("bench: batch of 4096 expressions")
         detail["batch_4096"] = batch_detail(fx, torch, stream, 20)
         torch.cuda.empty_cache()
@@ -373,6 +446,11 @@ def main():
     if not a.no_cpu:
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline()
+        if not a.no_extra:
+            log("bench: CPU oracle on one core")
+            one = cpu_baseline(cols_sample=COLS // 16, min_seconds=5.0, threads=1)
+            detail["cpu_oracle_1_core"] = {"value": one["value"], "unit": one["unit"],
+                                           "sample": one["sample"]}
 
     line = {
         "metric": "fused-expr HBM GB/s (% of peak) + speedup vs unfused, FP32 & BF16 storage",

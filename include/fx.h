@@ -216,6 +216,35 @@ int fx_paper_expr(int which, fx_dtype dt, const void* const* inputs, const doubl
 int fx_addn(fx_dtype dt, const void* const* inputs, int32_t n, void* Z, fx_shape shape,
             const fx_launch* cfg, void* stream);
 
+/* The paper's expressions over strided views (Sec. 4; Sec. 3 gives the
+ * transposed access, row and column swapped).  Inputs are m x n column-major
+ * matrices (leading dimension m, the `shape` argument); the result Z is dense:
+ *   FX_PAPER_ADDSUB2, _ADDSUB4: Z = sum of the centre submatrices (half the
+ *     rows and columns, from row (m - m/2)/2 and column (n - n/2)/2) of
+ *     2 or 4 inputs; Z is m/2 x n/2.
+ *   FX_PAPER_EXPR1: Z = 2 * (X.t() + Y) + 2 * (X + Y.t()); m == n; Z m x m.
+ *   FX_PAPER_EXPR2: Z = a * A + (B + C).t() + log(pow(D, 2)); m == n;
+ *     s[0] = a; Z m x m.
+ *   FX_PAPER_DIAGSUM: Z = (X.diag(-1) + X.diag(1)) % (Y.diag(-1) + Y.diag(1));
+ *     Z is a column of the length the two diagonals share,
+ *     min(min(m - 1, n), min(m, n - 1)) (m - 1 for a square matrix).
+ * Transposed operands are staged through LDS tiles so that every HBM read
+ * stays coalesced.  dt: FX_F32, FX_F64 or FX_BF16.  A non-square input for
+ * EXPR1/EXPR2 gives FX_E_SHAPE. */
+typedef enum {
+  FX_PAPER_ADDSUB2 = 16,
+  FX_PAPER_ADDSUB4 = 17,
+  FX_PAPER_EXPR1 = 18,
+  FX_PAPER_EXPR2 = 19,
+  FX_PAPER_DIAGSUM = 20
+} fx_paper_view_id;
+
+/* Result shape of a view expression over m x n inputs (FX_E_SHAPE if the
+ * inputs do not fit the expression). */
+int fx_paper_view_shape(int which, fx_shape shape, fx_shape* out);
+int fx_paper_view_expr(int which, fx_dtype dt, const void* const* inputs, const double* scalars,
+                       void* Z, fx_shape shape, void* stream);
+
 /* ---- unfused baseline: one kernel per operator ---------------------------
  * The same skeletons and launch configurations as the fused calls, but each
  * operator writes a full temporary, as toolkits without fusion do (Sec. 4). */

@@ -67,12 +67,19 @@ def lib():
         L.or_eval_u32.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P,
                                   ctypes.c_int64, P, P]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (for timing it)."""
+    lib().or_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -65,6 +65,15 @@ enum { OR_OK = 0, OR_EBAD = -1, OR_ENOMEM = -2 };
 #define CHUNK ((int64_t)1 << 18)
 #define ACCU_BLOCKS 64 /* fixed partition of a chunk for the full sum */
 
+/* Thread count for the timing of the oracle itself (not used by tests). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

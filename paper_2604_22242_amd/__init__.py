@@ -103,6 +103,8 @@ _SIGS = {
     "fx_colsum_xy": (_I, [_I, _P, _P, _P, Shape, _P, _SZ, _LP, _P]),
     "fx_paper_expr": (_I, [_I, _I, ctypes.POINTER(_P), ctypes.POINTER(_D), _P, Shape, _LP, _P]),
     "fx_addn": (_I, [_I, ctypes.POINTER(_P), ctypes.c_int32, _P, Shape, _LP, _P]),
+    "fx_paper_view_shape": (_I, [_I, Shape, ctypes.POINTER(Shape)]),
+    "fx_paper_view_expr": (_I, [_I, _I, ctypes.POINTER(_P), ctypes.POINTER(_D), _P, Shape, _P]),
     "fx_op_unary": (_I, [_I, _I, _P, _P, _I64, _LP, _P]),
     "fx_op_binary": (_I, [_I, _I, _P, _P, _P, _I64, _LP, _P]),
     "fx_op_scalar": (_I, [_I, _I, _P, _D, _P, _I64, _LP, _P]),
@@ -337,6 +339,26 @@ def fx_paper_expr(which, inputs, Z, shape, scalars=(), cfg=None, stream=None, dt
     dt = dtype_code(inputs[0]) if dt is None else dt
     return check(lib().fx_paper_expr(PAPER.get(which, which), dt, arr, sc, _ptr(Z), _shape(shape),
                                      _cfg(cfg), _stream(stream)))
+
+
+PAPER_VIEW = {"addsub2": 16, "addsub4": 17, "expr1": 18, "expr2": 19, "diagsum": 20}
+
+
+def fx_paper_view_shape(which, shape):
+    """(rows, cols) of a view expression's result over inputs of `shape`."""
+    out = Shape()
+    check(lib().fx_paper_view_shape(PAPER_VIEW.get(which, which), _shape(shape), ctypes.byref(out)))
+    return (out.n_rows, out.n_cols)
+
+
+def fx_paper_view_expr(which, inputs, Z, shape, scalars=(), stream=None, dt=None):
+    """One of the paper's strided-view expressions over m x n inputs
+    (shape = (m, n)); Z is dense, of fx_paper_view_shape(which, shape)."""
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    sc = (_D * max(1, len(scalars)))(*scalars) if scalars else None
+    dt = dtype_code(inputs[0]) if dt is None else dt
+    return check(lib().fx_paper_view_expr(PAPER_VIEW.get(which, which), dt, arr, sc, _ptr(Z),
+                                          _shape(shape), _stream(stream)))
 
 
 def fx_addn(inputs, Z, shape, cfg=None, stream=None):

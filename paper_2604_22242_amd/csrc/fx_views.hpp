@@ -1,0 +1,422 @@
+// Strided views: submatrix, transpose and diagonal leaves (Sec. 3 builds
+// the element access of a transposed matrix by swapping row and column in
+// the index; Sec. 4 uses the centre submatrix with half the rows and
+// columns, and diagonals).
+//
+//   Sub<T>    element (r, c) = p[off + r + c * ld]      (submatrix)
+//   Trans<T>  element (r, c) = p[off + c + r * ld]      (transposed matrix)
+//   Diag<T>   element (r, 0) = p[off + r * stride]      (diagonal, a vector)
+//
+// t(E) moves a transpose down to the leaves at compile time:
+// (B + C).t() is B.t() + C.t(), and a double transpose cancels.
+//
+// Evaluation.  A diagonal is a vector, so expressions over diagonals run
+// through the linear skeletons.  Expressions with Sub or Trans leaves run
+// through k_ew2d: one block per (16 * N) x 64 output tile, each thread a
+// vector of N consecutive rows in four columns.  Dense and submatrix leaves
+// are read straight from HBM (16-byte vectors when every view is aligned);
+// a transposed leaf's source tile is first staged in LDS by the whole block
+// with coalesced reads along the source's columns (column pitch 16 * N + 1
+// elements, so the strided LDS writes do not conflict), and the threads
+// then read their transposed vectors from LDS.
+#pragma once
+
+#include "fx_kernels.hpp"
+
+namespace fx {
+
+// ---- view leaves -------------------------------------------------------------
+
+template <class T> struct Sub : expr_tag {
+  using storage = T;
+  using ct = ct_t<T>;
+  const T* p;
+  int64_t off, ld, n_rows, n_cols;
+  __device__ __forceinline__ ct at(int64_t i) const {  // linear access (not on the fast path)
+    const int64_t r = i % n_rows, c = i / n_rows;
+    return static_cast<ct>(p[off + r + c * ld]);
+  }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<ct, N> x;
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = at(i + j);
+    return x;
+  }
+  void collect(leaf_info& li) const {
+    if (!p && n_rows * n_cols > 0) li.any_null = true;
+    li.add_shape(n_rows, n_cols);
+  }
+  static constexpr int kLeaves = 0;  // not de-duplicated
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R*, const uint8_t*, int64_t) const {}
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R*, int64_t i) const {
+    return at_vec<N, NT>(i);
+  }
+  void leaf_ids(leaf_id*, int&) const {}
+};
+
+template <class T> struct Trans : expr_tag {
+  using storage = T;
+  using ct = ct_t<T>;
+  const T* p;
+  int64_t off, ld, n_rows, n_cols;
+  __device__ __forceinline__ ct at(int64_t i) const {  // linear access (not on the fast path)
+    const int64_t r = i % n_rows, c = i / n_rows;
+    return static_cast<ct>(p[off + c + r * ld]);
+  }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<ct, N> x;
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = at(i + j);
+    return x;
+  }
+  void collect(leaf_info& li) const {
+    if (!p && n_rows * n_cols > 0) li.any_null = true;
+    li.add_shape(n_rows, n_cols);
+  }
+  static constexpr int kLeaves = 0;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R*, const uint8_t*, int64_t) const {}
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R*, int64_t i) const {
+    return at_vec<N, NT>(i);
+  }
+  void leaf_ids(leaf_id*, int&) const {}
+};
+
+template <class T> struct Diag : expr_tag {
+  using storage = T;
+  using ct = ct_t<T>;
+  const T* p;
+  int64_t off, stride, n_rows;
+  static constexpr int64_t n_cols = 1;
+  __device__ __forceinline__ ct at(int64_t i) const {
+    return static_cast<ct>(p[off + i * stride]);
+  }
+  template <int N, bool NT>
+  __device__ __forceinline__ lanes<ct, N> at_vec(int64_t i) const {
+    lanes<ct, N> x;
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.v[j] = at(i + j);
+    return x;
+  }
+  void collect(leaf_info& li) const {
+    if (!p && n_rows > 0) li.any_null = true;
+    li.add_shape(n_rows, 1);
+  }
+  static constexpr int kLeaves = 0;
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ void gather(R*, const uint8_t*, int64_t) const {}
+  template <int OFF, int N, bool NT, class R>
+  __device__ __forceinline__ lanes<ct, N> at_regs(const R*, int64_t i) const {
+    return at_vec<N, NT>(i);
+  }
+  void leaf_ids(leaf_id*, int&) const {}
+};
+
+// ---- front end ----------------------------------------------------------------
+
+// submat(X, r0, c0, rows, cols): rows x cols block of X from (r0, c0).
+template <class T> inline Sub<T> submat(const Leaf<T>& x, int64_t r0, int64_t c0, int64_t rows,
+                                        int64_t cols) {
+  Sub<T> s;
+  s.p = x.p;
+  s.off = r0 + c0 * x.n_rows;
+  s.ld = x.n_rows;
+  s.n_rows = rows;
+  s.n_cols = cols;
+  return s;
+}
+// diag(X, k): diagonal k of X (k > 0 above the main diagonal) as a column.
+template <class T> inline Diag<T> diag(const Leaf<T>& x, int64_t k) {
+  Diag<T> d;
+  d.p = x.p;
+  d.off = (k < 0 ? -k : 0) + (k > 0 ? k : 0) * x.n_rows;
+  d.stride = x.n_rows + 1;
+  d.n_rows = std::max<int64_t>(0, k >= 0 ? std::min(x.n_rows, x.n_cols - k)
+                                         : std::min(x.n_rows + k, x.n_cols));
+  return d;
+}
+
+// Is a leaf range inside its matrix?  (Host check for submat / diag.)
+template <class T> inline bool view_inside(const Leaf<T>& x, int64_t r0, int64_t c0,
+                                           int64_t rows, int64_t cols) {
+  return r0 >= 0 && c0 >= 0 && rows >= 0 && cols >= 0 && r0 + rows <= x.n_rows &&
+         c0 + cols <= x.n_cols;
+}
+
+template <class T> inline Trans<T> t(const Leaf<T>& x) {
+  Trans<T> r;
+  r.p = x.p;
+  r.off = 0;
+  r.ld = x.n_rows;
+  r.n_rows = x.n_cols;
+  r.n_cols = x.n_rows;
+  return r;
+}
+template <class T> inline Trans<T> t(const Sub<T>& x) {
+  Trans<T> r;
+  r.p = x.p;
+  r.off = x.off;
+  r.ld = x.ld;
+  r.n_rows = x.n_cols;
+  r.n_cols = x.n_rows;
+  return r;
+}
+template <class T> inline Sub<T> t(const Trans<T>& x) {
+  Sub<T> r;
+  r.p = x.p;
+  r.off = x.off;
+  r.ld = x.ld;
+  r.n_rows = x.n_cols;
+  r.n_cols = x.n_rows;
+  return r;
+}
+template <class Op, class A> inline auto t(const Unary<Op, A>& u) {
+  auto a = t(u.a);
+  return Unary<Op, decltype(a)>{{}, a};
+}
+template <class Op, class A, class B> inline auto t(const Binary<Op, A, B>& b) {
+  auto x = t(b.a);
+  auto y = t(b.b);
+  return Binary<Op, decltype(x), decltype(y)>{{}, x, y};
+}
+template <class Op, class A, bool LEFT> inline auto t(const Scalar<Op, A, LEFT>& s) {
+  auto a = t(s.a);
+  Scalar<Op, decltype(a), LEFT> r{{}, a, s.k};
+  r.aux = s.aux;
+  r.mode = s.mode;
+  return r;
+}
+template <class To, class A> inline auto t(const Convert<To, A>& cv) {
+  auto a = t(cv.a);
+  return Convert<To, decltype(a)>{{}, a};
+}
+template <class T> inline auto t(const dmat<T>& m) { return t(m.expr()); }
+
+// ---- traits -------------------------------------------------------------------
+
+// Number of transposed leaves (each gets an LDS tile), and whether the
+// expression needs the 2-D skeleton.
+template <class E> struct trans_count { static constexpr int value = 0; };
+template <class T> struct trans_count<Trans<T>> { static constexpr int value = 1; };
+template <class Op, class A> struct trans_count<Unary<Op, A>> : trans_count<A> {};
+template <class Op, class A, bool L> struct trans_count<Scalar<Op, A, L>> : trans_count<A> {};
+template <class To, class A> struct trans_count<Convert<To, A>> : trans_count<A> {};
+template <class Op, class A, class B> struct trans_count<Binary<Op, A, B>> {
+  static constexpr int value = trans_count<A>::value + trans_count<B>::value;
+};
+
+template <class E> struct needs_2d { static constexpr bool value = false; };
+template <class T> struct needs_2d<Sub<T>> { static constexpr bool value = true; };
+template <class T> struct needs_2d<Trans<T>> { static constexpr bool value = true; };
+template <class Op, class A> struct needs_2d<Unary<Op, A>> : needs_2d<A> {};
+template <class Op, class A, bool L> struct needs_2d<Scalar<Op, A, L>> : needs_2d<A> {};
+template <class To, class A> struct needs_2d<Convert<To, A>> : needs_2d<A> {};
+template <class Op, class A, class B> struct needs_2d<Binary<Op, A, B>> {
+  static constexpr bool value = needs_2d<A>::value || needs_2d<B>::value;
+};
+
+// ---- 2-D evaluation -------------------------------------------------------------
+
+constexpr int kTileCols = 64;
+constexpr int kTileThreads = 256;
+template <int N> constexpr int kTileRows = 16 * N;
+template <int N> constexpr int kTilePitch = 16 * N + 1;
+template <int N> constexpr int kTileBuf = kTileCols * kTilePitch<N>;
+
+// The tile being computed; NL is the vector width the LDS tiles were laid
+// out for (a scalar read inside a vector tile keeps that layout).
+template <class C, int NL> struct tile_ctx {
+  C* lds;
+  int64_t r0, c0;
+};
+
+// at2<TOFF, N>(e, r, c, x): rows r..r+N-1 of column c.  TOFF numbers the
+// transposed leaves depth-first (their LDS tiles).
+template <int TOFF, int N, class T, int NL>
+__device__ __forceinline__ lanes<ct_t<T>, N> at2(const Leaf<T>& e, int64_t r, int64_t c,
+                                                 const tile_ctx<ct_t<T>, NL>&) {
+  if constexpr (N > 1) return load_lanes<N, kNT>(e.p, r + c * e.n_rows);
+  lanes<ct_t<T>, N> v;
+  v.v[0] = static_cast<ct_t<T>>(e.p[r + c * e.n_rows]);
+  return v;
+}
+template <int TOFF, int N, class T, int NL>
+__device__ __forceinline__ lanes<ct_t<T>, N> at2(const Sub<T>& e, int64_t r, int64_t c,
+                                                 const tile_ctx<ct_t<T>, NL>&) {
+  if constexpr (N > 1) return load_lanes<N, kNT>(e.p, e.off + r + c * e.ld);
+  lanes<ct_t<T>, N> v;
+  v.v[0] = static_cast<ct_t<T>>(e.p[e.off + r + c * e.ld]);
+  return v;
+}
+template <int TOFF, int N, class T, int NL>
+__device__ __forceinline__ lanes<ct_t<T>, N> at2(const Trans<T>&, int64_t r, int64_t c,
+                                                 const tile_ctx<ct_t<T>, NL>& x) {
+  const ct_t<T>* buf = x.lds + TOFF * kTileBuf<NL> + (c - x.c0) * kTilePitch<NL> + (r - x.r0);
+  lanes<ct_t<T>, N> v;
+#pragma unroll
+  for (int j = 0; j < N; ++j) v.v[j] = buf[j];
+  return v;
+}
+template <int TOFF, int N, class T, int NL>
+__device__ __forceinline__ lanes<ct_t<T>, N> at2(const Diag<T>& e, int64_t r, int64_t,
+                                                 const tile_ctx<ct_t<T>, NL>&) {
+  return e.template at_vec<N, kNT>(r);
+}
+template <int TOFF, int N, class Op, class A, int NL>
+__device__ __forceinline__ lanes<typename A::ct, N> at2(const Unary<Op, A>& e, int64_t r, int64_t c,
+                                                        const tile_ctx<typename A::ct, NL>& x) {
+  lanes<typename A::ct, N> v = at2<TOFF, N>(e.a, r, c, x);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v.v[j] = Op::apply(v.v[j]);
+  return v;
+}
+template <int TOFF, int N, class Op, class A, bool L, int NL>
+__device__ __forceinline__ lanes<typename A::ct, N> at2(const Scalar<Op, A, L>& e, int64_t r,
+                                                        int64_t c,
+                                                        const tile_ctx<typename A::ct, NL>& x) {
+  lanes<typename A::ct, N> v = at2<TOFF, N>(e.a, r, c, x);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v.v[j] = e.apply1(v.v[j]);
+  return v;
+}
+template <int TOFF, int N, class Op, class A, class B, int NL>
+__device__ __forceinline__ lanes<typename A::ct, N> at2(const Binary<Op, A, B>& e, int64_t r,
+                                                        int64_t c,
+                                                        const tile_ctx<typename A::ct, NL>& x) {
+  lanes<typename A::ct, N> u = at2<TOFF, N>(e.a, r, c, x);
+  lanes<typename A::ct, N> w = at2<TOFF + trans_count<A>::value, N>(e.b, r, c, x);
+#pragma unroll
+  for (int j = 0; j < N; ++j) u.v[j] = Op::apply(u.v[j], w.v[j]);
+  return u;
+}
+template <int TOFF, int N, class To, class A, int NL>
+__device__ __forceinline__ lanes<To, N> at2(const Convert<To, A>& e, int64_t r, int64_t c,
+                                            const tile_ctx<To, NL>& x) {
+  static_assert(trans_count<A>::value == 0, "a transposed leaf below conv_to is not staged");
+  const tile_ctx<typename A::ct, NL> none{nullptr, x.r0, x.c0};
+  lanes<typename A::ct, N> v = at2<0, N>(e.a, r, c, none);
+  lanes<To, N> o;
+#pragma unroll
+  for (int j = 0; j < N; ++j) o.v[j] = static_cast<To>(v.v[j]);
+  return o;
+}
+
+// stage<TOFF, N>: every transposed leaf loads its source tile into LDS.
+template <int TOFF, int N, class E>
+__device__ __forceinline__ void stage(const E&, const tile_ctx<typename E::ct, N>&, int64_t, int64_t) {}
+template <int TOFF, int N, class T>
+__device__ __forceinline__ void stage(const Trans<T>& e, const tile_ctx<ct_t<T>, N>& x, int64_t rows,
+                                      int64_t cols) {
+  ct_t<T>* buf = x.lds + TOFF * kTileBuf<N>;
+  constexpr int TR = kTileRows<N>;
+  // idx -> (view columns cl..cl+N-1, view row rl); consecutive threads take
+  // consecutive view columns = consecutive source rows (coalesced); with
+  // N > 1 the host has checked that these N source elements form one
+  // aligned vector inside the source column
+  constexpr int CV = kTileCols / N;  // vectors per view row of the tile
+  for (int idx = threadIdx.x; idx < TR * CV; idx += kTileThreads) {
+    const int cl = (idx % CV) * N, rl = idx / CV;
+    const int64_t r = x.r0 + rl, c = x.c0 + cl;
+    if (r >= rows || c >= cols) continue;
+    if constexpr (N > 1) {
+      const lanes<ct_t<T>, N> v = load_lanes<N, kNT>(e.p, e.off + c + r * e.ld);
+#pragma unroll
+      for (int j = 0; j < N; ++j) buf[(cl + j) * kTilePitch<N> + rl] = v.v[j];
+    } else {
+      buf[cl * kTilePitch<N> + rl] = static_cast<ct_t<T>>(e.p[e.off + c + r * e.ld]);
+    }
+  }
+}
+template <int TOFF, int N, class Op, class A>
+__device__ __forceinline__ void stage(const Unary<Op, A>& e, const tile_ctx<typename A::ct, N>& x,
+                                      int64_t rows, int64_t cols) {
+  stage<TOFF, N>(e.a, x, rows, cols);
+}
+template <int TOFF, int N, class Op, class A, bool L>
+__device__ __forceinline__ void stage(const Scalar<Op, A, L>& e, const tile_ctx<typename A::ct, N>& x,
+                                      int64_t rows, int64_t cols) {
+  stage<TOFF, N>(e.a, x, rows, cols);
+}
+template <int TOFF, int N, class Op, class A, class B>
+__device__ __forceinline__ void stage(const Binary<Op, A, B>& e, const tile_ctx<typename A::ct, N>& x,
+                                      int64_t rows, int64_t cols) {
+  stage<TOFF, N>(e.a, x, rows, cols);
+  stage<TOFF + trans_count<A>::value, N>(e.b, x, rows, cols);
+}
+
+// Z (dense rows x cols) = E over a grid of tiles (blockIdx.x: tile row,
+// blockIdx.y: tile column).
+template <class E, class T, int N>
+__global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, int64_t rows,
+                                                      int64_t cols) {
+  using C = typename E::ct;
+  constexpr int KT = trans_count<E>::value;
+  __shared__ C lds[KT > 0 ? KT * kTileBuf<N> : 1];
+  const tile_ctx<C, N> x{lds, (int64_t)blockIdx.x * kTileRows<N>, (int64_t)blockIdx.y * kTileCols};
+  if constexpr (KT > 0) {
+    stage<0, N>(e, x, rows, cols);
+    __syncthreads();
+  }
+  const int rv = threadIdx.x % 16, cg = threadIdx.x / 16;
+  const int64_t r = x.r0 + rv * N;
+#pragma unroll
+  for (int q = 0; q < kTileCols / 16; ++q) {
+    const int64_t c = x.c0 + cg + 16 * q;
+    if (c >= cols || r >= rows) continue;
+    if (r + N <= rows) {
+      store_lanes<N, kNTS>(z, r + c * rows, at2<0, N>(e, r, c, x));
+    } else {
+      for (int j = 0; r + j < rows; ++j) z[r + j + c * rows] = static_cast<T>(at2<0, 1>(e, r + j, c, x).v[0]);
+    }
+  }
+}
+
+// Host: may every dense / submatrix leaf and the output be read N at a time?
+template <class T> inline bool vec_ok(const Leaf<T>& e, int N) {
+  return (reinterpret_cast<uintptr_t>(e.p) % (N * sizeof(T))) == 0 && e.n_rows % N == 0;
+}
+template <class T> inline bool vec_ok(const Sub<T>& e, int N) {
+  return (reinterpret_cast<uintptr_t>(e.p + e.off) % (N * sizeof(T))) == 0 && e.ld % N == 0;
+}
+template <class T> inline bool vec_ok(const Trans<T>& e, int N) {  // staged N source rows at a time
+  return (reinterpret_cast<uintptr_t>(e.p + e.off) % (N * sizeof(T))) == 0 && e.ld % N == 0 &&
+         e.n_cols % N == 0;
+}
+template <class T> inline bool vec_ok(const Diag<T>&, int) { return true; }
+template <class Op, class A> inline bool vec_ok(const Unary<Op, A>& e, int N) { return vec_ok(e.a, N); }
+template <class Op, class A, bool L> inline bool vec_ok(const Scalar<Op, A, L>& e, int N) {
+  return vec_ok(e.a, N);
+}
+template <class To, class A> inline bool vec_ok(const Convert<To, A>& e, int N) { return vec_ok(e.a, N); }
+template <class Op, class A, class B> inline bool vec_ok(const Binary<Op, A, B>& e, int N) {
+  return vec_ok(e.a, N) && vec_ok(e.b, N);
+}
+
+// Z = E for an expression with submatrix or transposed leaves.
+template <class E, class T>
+int eval_views(T* z, const E& e, hipStream_t st) {
+  int64_t rows, cols;
+  if (int rc = check_expr(e, &rows, &cols)) return rc;
+  if (rows * cols == 0) return FX_OK;
+  if (!z) return fail(FX_E_ARG, "NULL output pointer");
+  constexpr int NV = 16 / (int)sizeof(T) > 0 ? 16 / (int)sizeof(T) : 1;
+  const bool vec = vec_ok(e, NV) && rows % NV == 0 &&
+                   reinterpret_cast<uintptr_t>(z) % 16 == 0;
+  const int64_t tc = ceil_div(cols, kTileCols);
+  if (tc > 65535) return fail(FX_E_UNSUPPORTED, "%lld columns exceed the tile grid", (long long)cols);
+  if (vec) {
+    const dim3 grid((unsigned)ceil_div(rows, kTileRows<NV>), (unsigned)tc);
+    hipLaunchKernelGGL((k_ew2d<E, T, NV>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
+  } else {
+    const dim3 grid((unsigned)ceil_div(rows, kTileRows<1>), (unsigned)tc);
+    hipLaunchKernelGGL((k_ew2d<E, T, 1>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
+  }
+  return hip_check(hipGetLastError(), "k_ew2d launch");
+}
+
+}  // namespace fx
