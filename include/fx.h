@@ -326,23 +326,28 @@ typedef enum {
   FX_TI_DIV_S, FX_TI_DIV_I,   /* acc = acc / y */
   FX_TI_RDIV_S, FX_TI_RDIV_I, /* acc = y / acc */
   FX_TI_NEG, FX_TI_ABS, FX_TI_EXP, FX_TI_SQRT, /* acc = f(acc) */
-  /* modifier bits or-ed into the opcode of an instruction that reads acc:
-   * first acc = |acc|, then acc = -acc, then the operation (abs and neg
-   * nodes are folded into their consumer this way) */
+  FX_TI_STLD,   /* s[slot] = acc, then acc = s[slot2] */
+  /* modifier bits or-ed into the opcode of an instruction that reads acc,
+   * applied in this order before the operation: acc = s[slot2] (a load
+   * folded into its consumer), acc = |acc|, acc = -acc (abs and neg nodes
+   * are folded into their consumer this way) */
   FX_TI_ABS_IN = 0x100,
-  FX_TI_NEG_IN = 0x200
+  FX_TI_NEG_IN = 0x200,
+  FX_TI_LD_IN = 0x400
 } fx_tape_opcode;
 
 /* Copy up to `cap` instructions of t into op[] (opcode | modifier bits),
- * slot[] and imm[] (any may be NULL when cap is 0); returns the instruction
- * count, or a negative fx_status for a NULL tape. */
-int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, double* imm, int32_t cap);
+ * slot[], slot2[] and imm[] (any may be NULL when cap is 0); returns the
+ * instruction count, or a negative fx_status for a NULL tape. */
+int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* slot2, double* imm,
+                        int32_t cap);
 
 /* Evaluate tape t over inputs[0..n_inputs) (n_inputs >= the tape's inputs,
  * all of storage dtype dt and shape `shape`).  kind 0: element-wise, `out`
  * has the storage dtype; FX_R_ACCU / FX_R_NORM: one double; FX_R_COLSUM /
  * FX_R_ROWSUM: accumulator dtype vector.  ws as for the fused reductions
- * (fx_workspace_bytes of the same kind). */
+ * (fx_workspace_bytes of the same kind).  A zero EPT in cfg means 2 for element-wise
+ * tapes (the interpreter runs both vectors in one pass). */
 int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);
@@ -375,7 +380,8 @@ typedef struct {
 typedef struct fx_batch fx_batch;
 
 /* Build a batch (synchronous: allocates and uploads its device tables, owned
- * by the batch).  cfg: block / ept / vec_bytes as elsewhere, split = grid of
+ * by the batch).  cfg: block / ept / vec_bytes as elsewhere (0 = 256 threads,
+ * EPT 2, 16-byte vectors), split = grid of
  * the persistent kernel (0 = 8 blocks per CU); tile_elems: elements per tile
  * (0 = 16384; rounded up to whole block passes).  Item pointers must stay
  * valid while the batch is used. */

@@ -114,7 +114,7 @@ _SIGS = {
     "fx_tape_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, ctypes.POINTER(_P)]),
     "fx_tape_destroy": (None, [_P]),
     "fx_tape_describe": (_I, [_P, ctypes.POINTER(TapeInfo)]),
-    "fx_tape_program": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int32]),
+    "fx_tape_program": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int32]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
@@ -453,25 +453,28 @@ def fx_tape_describe(tape: Tape) -> dict:
 
 TAPE_OPCODES = ("LD", "LDI", "ST", "ADD_S", "ADD_I", "SUB_S", "SUB_I", "RSUB_S", "RSUB_I",
                 "MUL_S", "MUL_I", "DIV_S", "DIV_I", "RDIV_S", "RDIV_I", "NEG", "ABS", "EXP",
-                "SQRT")
-TAPE_ABS_IN, TAPE_NEG_IN = 0x100, 0x200
+                "SQRT", "STLD")
+TAPE_ABS_IN, TAPE_NEG_IN, TAPE_LD_IN = 0x100, 0x200, 0x400
 
 
 def fx_tape_program(tape: Tape):
-    """The compiled instructions as a list of (opcode name, slot, immediate);
-    input modifiers are appended to the name ("SQRT|abs": sqrt(|acc|))."""
-    n = lib().fx_tape_program(tape.handle, None, None, None, 0)
+    """The compiled instructions as a list of (opcode name, slot, slot2,
+    immediate); input modifiers are appended to the name in the order they
+    apply ("ADD_I|ld|abs": acc = |s[slot2]| + imm)."""
+    n = lib().fx_tape_program(tape.handle, None, None, None, None, 0)
     if n < 0:
         check(-n)
     op = (ctypes.c_uint16 * max(1, n))()
     slot = (ctypes.c_uint8 * max(1, n))()
+    slot2 = (ctypes.c_uint8 * max(1, n))()
     imm = (ctypes.c_double * max(1, n))()
-    lib().fx_tape_program(tape.handle, op, slot, imm, n)
+    lib().fx_tape_program(tape.handle, op, slot, slot2, imm, n)
 
     def name(code):
-        mods = ("|abs" if code & TAPE_ABS_IN else "") + ("|neg" if code & TAPE_NEG_IN else "")
+        mods = (("|ld" if code & TAPE_LD_IN else "") + ("|abs" if code & TAPE_ABS_IN else "") +
+                ("|neg" if code & TAPE_NEG_IN else ""))
         return TAPE_OPCODES[code & 0xFF] + mods
-    return [(name(op[i]), slot[i], imm[i]) for i in range(n)]
+    return [(name(op[i]), slot[i], slot2[i], imm[i]) for i in range(n)]
 
 
 def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stream=None,

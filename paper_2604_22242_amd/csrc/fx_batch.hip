@@ -213,7 +213,7 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   I = fx_batch_info{};
   I.count = count;
   I.block = c.block ? c.block : 256;
-  I.ept = c.ept ? c.ept : 1;
+  I.ept = c.ept ? c.ept : 2;  // two vectors per thread: one interpreter pass of 8 lanes
   I.vec_bytes = (c.vec_bytes ? std::max(c.vec_bytes, elem) : 16);
   if (addr_or & 15) I.vec_bytes = elem;  // every pointer must be 16-byte aligned for vectors
   b->vec = I.vec_bytes / elem;

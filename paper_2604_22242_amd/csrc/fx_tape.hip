@@ -189,6 +189,39 @@ struct compiler {
   }
 };
 
+// Peephole over the emitted program: "ST a; LD b" becomes one STLD a, b, and
+// a plain "LD b" followed by an instruction that reads the accumulator is
+// folded into it as the load-in modifier (slot b in the high byte of a).
+// Each removed instruction saves one fetch and one dispatch per lane group.
+void fuse_loads(tape_prog* p) {
+  int o = 0;
+  for (int i = 0; i < p->n_ins; ++i) {
+    tape_ins I = p->ins[i];
+    const bool has_next = i + 1 < p->n_ins;
+    const tape_ins N = has_next ? p->ins[i + 1] : tape_ins{};
+    const int op = I.op & 0xFF, nop = N.op & 0xFF;
+    if (has_next && op == A_ST && nop == A_LD && (N.op & ~0xFF) == 0) {
+      I.op = (uint16_t)((I.op & ~0xFF) | A_STLD);  // the ST's abs/neg modifiers stay
+      I.a = (uint16_t)((I.a & 0xFF) | ((N.a & 0xFF) << 8));
+      p->ins[o++] = I;
+      ++i;
+      continue;
+    }
+    if (has_next && op == A_LD && (I.op & ~0xFF) == 0 && nop != A_LD && nop != A_LDI &&
+        nop != A_STLD && !(N.op & kLdIn)) {
+      tape_ins F = N;
+      F.op = (uint16_t)(N.op | kLdIn);
+      F.a = (uint16_t)((N.a & 0xFF) | ((I.a & 0xFF) << 8));
+      p->ins[o++] = F;
+      ++i;
+      continue;
+    }
+    p->ins[o++] = I;
+  }
+  for (int i = o; i <= p->n_ins && i <= kTapeMaxIns; ++i) p->ins[i] = tape_ins{};
+  p->n_ins = o;
+}
+
 }  // namespace
 
 int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info* info) {
@@ -241,6 +274,7 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
   if (root.w != IN_ACC) c.load(root);  // a leaf, a constant or a stored node
   c.flush();                           // a root abs / neg
   if (c.status != FX_OK) return c.status;
+  fuse_loads(prog);
   if (c.max_slot > kTapeMaxSlots)
     return fail(FX_E_UNSUPPORTED, "tape needs %d live slots (at most %d)", c.max_slot, kTapeMaxSlots);
   prog->n_slots = c.max_slot;
@@ -278,13 +312,15 @@ int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out) {
 
 void fx_tape_destroy(fx_tape* t) { delete t; }
 
-int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, double* imm, int32_t cap) {
+int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* slot2, double* imm,
+                        int32_t cap) {
   if (!t) return -fail(FX_E_ARG, "NULL tape");
   const int32_t n = t->prog.n_ins;
-  if (cap > 0 && (!op || !slot || !imm)) return -fail(FX_E_ARG, "NULL output array");
+  if (cap > 0 && (!op || !slot || !slot2 || !imm)) return -fail(FX_E_ARG, "NULL output array");
   for (int32_t i = 0; i < n && i < cap; ++i) {
     op[i] = t->prog.ins[i].op;
-    slot[i] = (uint8_t)t->prog.ins[i].a;
+    slot[i] = (uint8_t)(t->prog.ins[i].a & 0xFF);
+    slot2[i] = (uint8_t)(t->prog.ins[i].a >> 8);
     imm[i] = t->prog.ins[i].kd;
   }
   return n;

@@ -43,22 +43,24 @@ enum : uint8_t {
   A_DIV_S, A_DIV_I,    // acc = acc / y
   A_RDIV_S, A_RDIV_I,  // acc = y / acc
   A_NEG, A_ABS, A_EXP, A_SQRT,  // acc = f(acc)
+  A_STLD,                        // s[a] = acc, then acc = s[a2]
   A_N_OPS
 };
 static_assert(A_LD == FX_TI_LD && A_ST == FX_TI_ST && A_ADD_S == FX_TI_ADD_S &&
-                  A_RDIV_I == FX_TI_RDIV_I && A_SQRT == FX_TI_SQRT,
+                  A_RDIV_I == FX_TI_RDIV_I && A_SQRT == FX_TI_SQRT && A_STLD == FX_TI_STLD,
               "interpreter opcodes follow fx_tape_opcode");
-// Input modifiers of an instruction that reads the accumulator: acc = |acc|
-// and then acc = -acc before the operation.  The compiler folds abs and neg
-// nodes into the next instruction this way (both are exact).
-constexpr uint16_t kAbsIn = FX_TI_ABS_IN, kNegIn = FX_TI_NEG_IN;
+// Input modifiers of an instruction that reads the accumulator, applied in
+// this order before the operation: acc = s[a2] (a load folded into its
+// consumer), acc = |acc|, acc = -acc (abs and neg nodes folded likewise;
+// both are exact).
+constexpr uint16_t kAbsIn = FX_TI_ABS_IN, kNegIn = FX_TI_NEG_IN, kLdIn = FX_TI_LD_IN;
 
 // op and a fill the first 32-bit word together so that a fetch through a
 // device pointer (batches) stays one scalar load: a narrower field would let
 // the compiler shrink it to a 16-bit vector load, whose wait also waits for
 // every input load in flight.
 struct tape_ins {
-  uint16_t op, a;  // a: slot index (LD, ST and S-forms)
+  uint16_t op, a;  // a: slot index (LD, ST and S-forms) | second slot a2 << 8
   float kf;        // immediate for FP32 compute
   double kd;       // immediate for FP64 compute
 };
@@ -88,20 +90,26 @@ constexpr int kTapeSmallSlots = 8;
 template <int S> constexpr int kLanesPerFile = 16 / S;
 template <int S, int L> constexpr int kFiles = (L + kLanesPerFile<S> - 1) / kLanesPerFile<S>;
 #define FX_SLOT(f, j, a) f[(j) / P][(a) * P + (j) % P]
-template <class C> constexpr int kPassLanes = sizeof(C) == 4 ? 4 : 2;
+// Lanes interpreted per pass: every interpreted instruction is one fetch and
+// one dispatch for all of them.
+#ifndef FX_TAPE_PASS_LANES
+#define FX_TAPE_PASS_LANES 8
+#endif
+template <class C> constexpr int kPassLanes = sizeof(C) == 4 ? FX_TAPE_PASS_LANES
+                                                              : (FX_TAPE_PASS_LANES + 1) / 2;
 
 // acc[j] = OP(acc[j], y) for slot and immediate operands (and the reversed
 // forms): each case computes straight into the accumulator so no operand
 // copies survive the branch merge.
 #define FX_TAPE_BIN(NAME, OPK)                                                     \
   case A_##NAME##_S:                                                              \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], FX_SLOT(s, j, I.a)); \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], FX_SLOT(s, j, a)); \
     break;                                                                        \
   case A_##NAME##_I:                                                              \
     _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], k); \
     break;                                                                        \
   case A_R##NAME##_S:                                                             \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(FX_SLOT(s, j, I.a), acc[j]); \
+    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(FX_SLOT(s, j, a), acc[j]); \
     break;                                                                        \
   case A_R##NAME##_I:                                                             \
     _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(k, acc[j]); \
@@ -124,7 +132,11 @@ __device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[
     const tape_ins next = prog.ins[pc + 1];
     const C k = tape_imm<C>(I);
     const unsigned op = I.op;
-    if (op & (kAbsIn | kNegIn)) {
+    const unsigned a = I.a & 0xFFu, a2 = I.a >> 8;
+    if (op & (kAbsIn | kNegIn | kLdIn)) {
+      if (op & kLdIn)
+#pragma unroll
+        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, a2);
       if (op & kAbsIn)
 #pragma unroll
         for (int j = 0; j < L; ++j) acc[j] = op_abs::apply(acc[j]);
@@ -135,7 +147,7 @@ __device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[
     switch (op & 0xFFu) {
       case A_LD:
 #pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, I.a);
+        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, a);
         break;
       case A_LDI:
 #pragma unroll
@@ -143,11 +155,11 @@ __device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[
         break;
       case A_ST:
 #pragma unroll
-        for (int j = 0; j < L; ++j) FX_SLOT(s, j, I.a) = acc[j];
+        for (int j = 0; j < L; ++j) FX_SLOT(s, j, a) = acc[j];
         break;
       case A_ADD_S:
 #pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], FX_SLOT(s, j, I.a));
+        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], FX_SLOT(s, j, a));
         break;
       case A_ADD_I:
 #pragma unroll
@@ -156,7 +168,7 @@ __device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[
       FX_TAPE_BIN(SUB, op_sub)
       case A_MUL_S:
 #pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], FX_SLOT(s, j, I.a));
+        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], FX_SLOT(s, j, a));
         break;
       case A_MUL_I:
 #pragma unroll
@@ -167,6 +179,13 @@ __device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[
       FX_TAPE_UN(ABS, op_abs)
       FX_TAPE_UN(EXP, op_exp)
       FX_TAPE_UN(SQRT, op_sqrt)
+      case A_STLD:
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          FX_SLOT(s, j, a) = acc[j];
+          acc[j] = FX_SLOT(s, j, a2);
+        }
+        break;
       default:
         break;
     }
@@ -251,8 +270,19 @@ __device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF, SLOTS>& e, in
     if (q < n_in)
 #pragma unroll
       for (int k = 0; k < EPT; ++k) in[k][q] = load_lanes<N, kNT>(e.p[q], base + k * stride);
+  // the EPT vectors are interpreted together, in passes of kPassLanes lanes
+  lanes<C, N * EPT> flat[kTapeMaxIn];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) r[k] = e.template interpret<N>(in[k]);
+  for (int q = 0; q < kTapeMaxIn; ++q)
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+#pragma unroll
+      for (int j = 0; j < N; ++j) flat[q].v[k * N + j] = in[k][q].v[j];
+  const lanes<C, N * EPT> out = e.template interpret<N * EPT>(flat);
+#pragma unroll
+  for (int k = 0; k < EPT; ++k)
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[k].v[j] = out.v[k * N + j];
 }
 
 template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static constexpr int value = 2; };
@@ -273,7 +303,13 @@ int tape_eval_impl(const tape_prog& prog, const void* const* inputs, fx_shape s,
   e.n_cols = s.n_cols;
   e.prog = prog;
   switch (kind) {
-    case 0: return eval(static_cast<T*>(out), e, cfg, st);
+    case 0: {
+      // two vectors per thread by default: the interpreter runs them as one
+      // pass of kPassLanes lanes, halving fetches and dispatches per element
+      fx_launch c = cfg ? *cfg : fx_launch{0, 0, 0, 0};
+      if (c.ept == 0) c.ept = 2;
+      return eval(static_cast<T*>(out), e, &c, st);
+    }
     case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, cfg, st);
     case FX_R_NORM: return reduce_full<map_sq>(e, out, ws, ws_bytes, cfg, st);
     case FX_R_COLSUM: case FX_R_ROWSUM:

@@ -130,6 +130,64 @@ def evaluate(m: Model, records, cus=256):
             "unmeasured_predictions": missing}
 
 
+# The matrix workload's expression trees (Z = (X+Y) % exp(-abs(W)) / (1 + X%X),
+# and X - Y for the norm) as node lists, for the model's features.
+C2_NODES = [("leaf", -1, -1, 0, 0.0), ("leaf", -1, -1, 1, 0.0), ("add", 0, 1, -1, 0.0),
+            ("leaf", -1, -1, 2, 0.0), ("abs", 3, -1, -1, 0.0), ("neg", 4, -1, -1, 0.0),
+            ("exp", 5, -1, -1, 0.0), ("mul", 2, 6, -1, 0.0), ("const", -1, -1, -1, 1.0),
+            ("mul", 0, 0, -1, 0.0), ("add", 8, 9, -1, 0.0), ("div", 7, 10, -1, 0.0)]
+DIFF_NODES = [("leaf", -1, -1, 0, 0.0), ("leaf", -1, -1, 1, 0.0), ("sub", 0, 1, -1, 0.0)]
+
+
+def et_check(m: Model, cus: int, rows=8192, cols=8192, reps=5):
+    """Transfer check: the model (trained on run-time tapes) picks launch
+    configurations for the compile-time kernels of the FP32 matrix workload;
+    each result's whole grid is timed to find its own best."""
+    import statistics
+    import torch
+    import synth
+    from . import (R_COLSUM, R_NORM, Tape, fx_c2_colsum, fx_c2_z, fx_norm_fro_diff,
+                   fx_workspace_bytes, F32)
+    from .tune import features, grid
+    shape, n = (rows, cols), rows * cols
+    X, Y, W = [torch.from_numpy(synth.fill(2, t, n, "f32")).cuda() for t in range(3)]
+    Z = torch.empty(n, device="cuda")
+    cs = torch.empty(cols, device="cuda")
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    runs = {"z": (C2_NODES, None, 0, lambda c, ws: fx_c2_z(X, Y, W, Z, shape, cfg=c)),
+            "colsum": (C2_NODES, "colsum", R_COLSUM,
+                       lambda c, ws: fx_c2_colsum(X, Y, W, cs, shape, ws, cfg=c)),
+            "norm": (DIFF_NODES, "norm", R_NORM,
+                     lambda c, ws: fx_norm_fro_diff(X, Y, nrm, shape, ws, cfg=c))}
+    out = {}
+    for name, (nodes, red, kind, fn) in runs.items():
+        cfgs = [c for c, _ in grid(red, "f32", cus)]
+        wsb = max(fx_workspace_bytes(kind, F32, shape, c) for c in cfgs) if kind else 0
+        ws = torch.zeros(max(wsb, 8), dtype=torch.uint8, device="cuda") if kind else None
+        times = []
+        for c in cfgs:
+            for _ in range(2):
+                fn(c, ws)
+            ev = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn(c, ws)
+                b.record()
+                ev.append((a, b))
+            torch.cuda.synchronize()
+            times.append(statistics.median(a.elapsed_time(b) for a, b in ev))
+        info = Tape(nodes).info()
+        pick = config_of(m.choose(features(info, "f32", shape, red)), red, "f32", cus)
+        best = min(times)
+        out[name] = {"best_ms": round(best, 5), "best_config": list(cfgs[times.index(best)]),
+                     "model_config": list(pick), "model_ms": round(times[cfgs.index(pick)], 5),
+                     "model_vs_best": round(times[cfgs.index(pick)] / best, 4),
+                     "default_ms": round(times[-1], 5),
+                     "default_vs_best": round(times[-1] / best, 4)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", nargs="+", required=True)
@@ -137,6 +195,8 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--et-check", action="store_true",
+                    help="also apply the model to the compile-time matrix-workload kernels")
     a = ap.parse_args(argv)
     tr = [r for p in a.train for r in load_db(p).values()]
     ho = [r for p in a.heldout for r in load_db(p).values()]
@@ -148,6 +208,8 @@ def main(argv=None):
            "loss_curve": curve, "train_fit": evaluate(m, tr, cus)}
     if ho:
         rep["heldout"] = evaluate(m, ho, cus)
+    if a.et_check:
+        rep["compile_time_kernels"] = et_check(m, cus)
     if a.out:
         save(m, a.out)
     print(json.dumps(rep, indent=1), flush=True)

@@ -149,3 +149,22 @@ def test_batch_full_workload():
             continue
         worst = max(worst, rep["max_err_over_allowed"])
     print("batch worst err/allowed %.3f" % worst, flush=True)
+
+
+def test_batch_with_a_sixteen_slot_program():
+    """One item needing more than 8 slots moves the whole batch to the
+    16-slot kernel; results still match the single tapes and the oracle."""
+    torch, fx = need_gpu()
+    from test_gpu_tape import _balanced
+    tset = trees.batch_set(24)
+    tset.append({"id": 24, "nodes": _balanced(5), "n_inputs": 4, "n": 5000, "reduce": None})
+    tset.append({"id": 25, "nodes": _balanced(5), "n_inputs": 4, "n": 7001, "reduce": "accu"})
+    items, host = _build(fx, torch, tset, "f32", 6)
+    b = fx.Batch(items, fx.F32, tile_elems=2048)
+    b.launch()
+    torch.cuda.synchronize()
+    for t, it, h in zip(tset, items, host):
+        red = "accu" if it[4] else None
+        v, mu = oracle.evaluate(oracle_expr(t["nodes"]), h, "f32", shape=(t["n"], 1), reduce=red)
+        got = it[2].cpu().numpy() if it[4] else from_dev(it[2], "f32")
+        assert_close(got, v, mu, "f32", "16-slot batch tree %d" % t["id"])

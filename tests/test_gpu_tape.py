@@ -112,3 +112,33 @@ def test_constant_tree():
                     dt=fx.F32)
     torch.cuda.synchronize()
     assert (out == 4.0).all().item() and s.item() == 4000.0
+
+
+def _balanced(depth, k=4):
+    """A full binary tree over exp(leaf) with the four operators in turn:
+    every operand needs code, so the program needs depth + 4 slots."""
+    nodes, level = [], []
+    for i in range(2 ** depth):
+        nodes.append(("leaf", -1, -1, i % k, 0.0))
+        nodes.append(("exp", len(nodes) - 1, -1, -1, 0.0))
+        level.append(len(nodes) - 1)
+    ops, j = ("add", "sub", "mul", "div"), 0
+    while len(level) > 1:
+        nxt = []
+        for a, b in zip(level[::2], level[1::2]):
+            nodes.append((ops[j % 4], a, b, -1, 0.0))
+            j += 1
+            nxt.append(len(nodes) - 1)
+        level = nxt
+    return nodes
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
+def test_sixteen_slot_programs(dtype):
+    """A program needing more than 8 slots runs on the 16-slot file."""
+    torch, fx = need_gpu()
+    nodes = _balanced(5)
+    assert fx.Tape(nodes).info()["n_slots"] > 8
+    _run(fx, torch, nodes, 4, 9, 0, dtype, (33333, 1), 0)
+    _run(fx, torch, nodes, 4, 9, 0, dtype, (40001, 1), fx.R_ACCU)
+    _run(fx, torch, nodes, 4, 9, 0, dtype, (129, 131), fx.R_COLSUM)

@@ -11,8 +11,9 @@ pytestmark = pytest.mark.gpu
 
 ARITY = {"addsub2": 2, "addsub4": 4, "expr1": 2, "expr2": 4, "diagsum": 2}
 # square sizes: one tile, several tiles with ragged edges, odd rows (the
-# scalar kernel: rows not a multiple of the vector width)
-SIZES = [1, 2, 7, 64, 65, 130, 257, 1000]
+# scalar kernel: rows not a multiple of the vector width); FP32 squares with
+# rows a multiple of 4 span 1, 2, 3, 16 and 17 tiles a side
+SIZES = [1, 2, 7, 64, 65, 128, 130, 192, 257, 1000, 1028]
 
 
 def _inputs(name, m, n, dtype, seed=21):

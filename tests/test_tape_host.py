@@ -29,47 +29,48 @@ def test_compile_simple(fx):
     assert info["op_count"][:4] == [1, 0, 2, 0] and info["n_consts"] == 1
     # X % Y into the accumulator, kept in slot 3 while 2 * W is computed
     # (the constant is an immediate), then the sum
-    assert t.program() == [("LD", 0, 0.0), ("MUL_S", 1, 0.0), ("ST", 3, 0.0),
-                           ("LD", 2, 0.0), ("MUL_I", 0, 2.0), ("ADD_S", 3, 0.0)]
-    assert info["n_instructions"] == 6 and info["n_slots"] == 4
+    # (the loads fold into their consumers: ST 3 + LD 2 is one STLD)
+    assert t.program() == [("MUL_S|ld", 1, 0, 0.0), ("STLD", 3, 2, 0.0), ("MUL_I", 0, 0, 2.0),
+                           ("ADD_S", 3, 0, 0.0)]
+    assert info["n_instructions"] == 4 and info["n_slots"] == 4
 
 
 def test_constant_and_leaf_trees(fx):
-    assert fx.Tape([("const", -1, -1, -1, 3.0)]).program() == [("LDI", 0, 3.0)]
+    assert fx.Tape([("const", -1, -1, -1, 3.0)]).program() == [("LDI", 0, 0, 3.0)]
     leaf = fx.Tape([("leaf", -1, -1, 0, 0)])
-    assert leaf.program() == [("LD", 0, 0.0)] and leaf.info()["n_inputs"] == 1
+    assert leaf.program() == [("LD", 0, 0, 0.0)] and leaf.info()["n_inputs"] == 1
     two = fx.Tape([("const", -1, -1, -1, 1.0), ("const", -1, -1, -1, 2.0),
                    ("sub", 0, 1, -1, 0)])
-    assert two.program() == [("LDI", 0, 1.0), ("SUB_I", 0, 2.0)]
+    assert two.program() == [("LDI", 0, 0, 1.0), ("SUB_I", 0, 0, 2.0)]
     # an immediate on the left of a slot: the reversed form keeps the order
     rev = fx.Tape([("const", -1, -1, -1, 1.0), ("leaf", -1, -1, 0, 0), ("div", 0, 1, -1, 0)])
-    assert rev.program() == [("LD", 0, 0.0), ("RDIV_I", 0, 1.0)]
+    assert rev.program() == [("RDIV_I|ld", 0, 0, 1.0)]
 
 
 def test_abs_and_neg_fold_into_the_consumer(fx):
     X = ("leaf", -1, -1, 0, 0.0)
     # the generator's guards: sqrt(|x|), exp(0 - |x|), x / (1 + |y|)
     t = fx.Tape([X, ("abs", 0, -1, -1, 0), ("sqrt", 1, -1, -1, 0)])
-    assert t.program() == [("LD", 0, 0.0), ("SQRT|abs", 0, 0.0)]
+    assert t.program() == [("SQRT|ld|abs", 0, 0, 0.0)]
     t = fx.Tape([X, ("const", -1, -1, -1, 0.0), ("abs", 0, -1, -1, 0), ("sub", 1, 2, -1, 0),
                  ("exp", 3, -1, -1, 0)])
-    assert t.program() == [("LD", 0, 0.0), ("RSUB_I|abs", 0, 0.0), ("EXP", 0, 0.0)]
+    assert t.program() == [("RSUB_I|ld|abs", 0, 0, 0.0), ("EXP", 0, 0, 0.0)]
     t = fx.Tape([X, ("leaf", -1, -1, 1, 0.0), ("const", -1, -1, -1, 1.0), ("abs", 1, -1, -1, 0),
                  ("add", 2, 3, -1, 0), ("div", 0, 4, -1, 0)])
-    assert t.program() == [("LD", 1, 0.0), ("ADD_I|abs", 0, 1.0), ("RDIV_S", 0, 0.0)]
+    assert t.program() == [("ADD_I|ld|abs", 0, 1, 1.0), ("RDIV_S", 0, 0, 0.0)]
     # compositions: -(-x) vanishes, -|x| keeps both, |-x| is |x|; a root
     # modifier becomes an instruction of its own
     nn = fx.Tape([X, ("neg", 0, -1, -1, 0), ("neg", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
-    assert nn.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0)]
+    assert nn.program() == [("EXP|ld", 0, 0, 0.0)]
     na = fx.Tape([X, ("abs", 0, -1, -1, 0), ("neg", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
-    assert na.program() == [("LD", 0, 0.0), ("EXP|abs|neg", 0, 0.0)]
+    assert na.program() == [("EXP|ld|abs|neg", 0, 0, 0.0)]
     an = fx.Tape([X, ("neg", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("exp", 2, -1, -1, 0)])
-    assert an.program() == [("LD", 0, 0.0), ("EXP|abs", 0, 0.0)]
+    assert an.program() == [("EXP|ld|abs", 0, 0, 0.0)]
     root = fx.Tape([X, ("exp", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("neg", 2, -1, -1, 0)])
-    assert root.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0), ("ABS", 0, 0.0), ("NEG", 0, 0.0)]
+    assert root.program() == [("EXP|ld", 0, 0, 0.0), ("ABS", 0, 0, 0.0), ("NEG", 0, 0, 0.0)]
     # a shared abs node is stored with its modifier applied
     sh = fx.Tape([X, ("exp", 0, -1, -1, 0), ("abs", 1, -1, -1, 0), ("mul", 2, 2, -1, 0)])
-    assert sh.program() == [("LD", 0, 0.0), ("EXP", 0, 0.0), ("ST|abs", 1, 0.0), ("MUL_S", 1, 0.0)]
+    assert sh.program() == [("EXP|ld", 0, 0, 0.0), ("ST|abs", 1, 0, 0.0), ("MUL_S", 1, 0, 0.0)]
 
 
 def test_dag_shared_node(fx):
@@ -79,8 +80,8 @@ def test_dag_shared_node(fx):
     t = fx.Tape(nodes)
     assert t.info()["op_count"][:3] == [1, 1, 1]
     # t is computed once and kept in a slot for its later uses
-    assert t.program() == [("LD", 0, 0.0), ("ADD_S", 1, 0.0), ("ST", 2, 0.0),
-                           ("MUL_S", 2, 0.0), ("SUB_S", 2, 0.0)]
+    assert t.program() == [("ADD_S|ld", 1, 0, 0.0), ("ST", 2, 0, 0.0), ("MUL_S", 2, 0, 0.0),
+                           ("SUB_S", 2, 0, 0.0)]
 
 
 @pytest.mark.parametrize("bad", [
@@ -141,8 +142,10 @@ def run_program(prog, inputs):
     for q, x in enumerate(inputs):
         slots[q] = x.astype(np.float64)
     acc = None
-    for name, s, k in prog:
+    for name, s, s2, k in prog:
         op, *mods = name.split("|")
+        if "ld" in mods:
+            acc = slots[s2].copy()
         if "abs" in mods:
             acc = np.abs(acc)
         if "neg" in mods:
@@ -154,6 +157,9 @@ def run_program(prog, inputs):
             acc = np.full(inputs[0].shape if inputs else (1,), k)
         elif op == "ST":
             slots[s] = acc.copy()
+        elif op == "STLD":
+            slots[s] = acc.copy()
+            acc = slots[s2].copy()
         elif op.startswith("ADD"):
             acc = acc + y
         elif op.startswith("SUB"):
