@@ -279,6 +279,44 @@ def paper_suite_detail(fx, torch, stream, reps):
     return {"expressions_10k": suite, "add_N_sweep_10k": sweep}
 
 
+def modes_detail(fx, torch, stream, reps):
+    """One expression three ways: compile-time template (the fused kernel),
+    run-time tape (interpreter) and run-time source (hipRTC-compiled at first
+    use).  The matrix workload's Z over 2^26 FP32 elements, and the deepest of
+    the first 200 generated tuning trees (depth <= 8) over 2^26 elements."""
+    import synth
+    from synth import trees
+    from paper_2604_22242_amd.model import C2_NODES
+    n = ROWS * COLS
+    ins = [torch.from_numpy(synth.fill(2, t, n, "f32")).cuda() for t in range(4)]
+    Z = torch.empty(n, device="cuda")
+    out = {}
+    r = fx.Rtc(C2_NODES, fx.F32)
+    tape = fx.Tape(C2_NODES)
+    out["c2_z"] = {
+        "compile_time_ms": round(event_ms(torch, stream, lambda: fx.fx_c2_z(
+            *ins[:3], Z, (ROWS, COLS), stream=stream), reps), 4),
+        "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
+            tape, ins[:3], Z, (n, 1), stream=stream), reps), 4),
+        "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
+            ins[:3], Z, stream=stream), reps), 4),
+        "hiprtc_compile_ms": round(r.compile_ms(), 1)}
+    best = max((trees.tuning_item(5, i) for i in range(200)),
+               key=lambda it: fx.Tape(it["nodes"]).info()["n_instructions"])
+    k = best["n_inputs"]
+    tape = fx.Tape(best["nodes"])
+    r = fx.Rtc(best["nodes"], fx.F32)
+    out["deep_tree"] = {
+        "tree": best["id"], "nodes": len(best["nodes"]),
+        "tape_instructions": tape.info()["n_instructions"],
+        "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
+            tape, ins[:k], Z, (n, 1), stream=stream), reps), 4),
+        "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
+            ins[:k], Z, stream=stream), reps), 4),
+        "hiprtc_compile_ms": round(r.compile_ms(), 1)}
+    return out
+
+
 def paper_views_detail(fx, torch, stream, reps):
     """The paper's strided-view expressions at its size, 10k x 10k FP32
     inputs (Sec. 4): centre-submatrix sums, expressions with transposes and
@@ -433,6 +471,9 @@ def main():
         detail["c1_2^20"] = c1_detail(fx, torch, stream, 50)
         log("bench: the paper's strided-view expressions, 10k x 10k")
         detail["paper_views"] = paper_views_detail(fx, torch, stream, 10)
+        torch.cuda.empty_cache()
+        log("bench: compile-time, tape and run-time source modes")
+        detail["modes"] = modes_detail(fx, torch, stream, 20)
         torch.cuda.empty_cache()
         log("bench: batch of 4096 expressions")
         detail["batch_4096"] = batch_detail(fx, torch, stream, 20)

@@ -352,6 +352,32 @@ int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);
 
+/* ---- run-time source mode -------------------------------------------------
+ * The paper's own mechanism (Sec. 3): the kernel source of an expression is
+ * generated, compiled through the driver at first use and reused.  Here a
+ * tree (the fx_node list of the tapes) becomes the HIP source of one fused
+ * element-wise kernel, compiled with hipRTC for gfx950 with the library's
+ * flags and cached per process by its text; the compiled kernel reads each
+ * input once and writes once, like a compile-time expression, without the
+ * interpreter's per-instruction cost.  FP32 and FP64 storage. */
+typedef struct fx_rtc fx_rtc;
+
+/* Generate and compile (or find in the cache) the kernel of nodes[0..n_nodes)
+ * for storage dtype dt.  Synchronous; needs no device.  Compilation errors
+ * give FX_E_HIP with the compiler log in fx_last_error. */
+int fx_rtc_create(const fx_node* nodes, int32_t n_nodes, fx_dtype dt, fx_rtc** out);
+void fx_rtc_destroy(fx_rtc* r);
+/* The generated source (NUL-terminated, truncated to cap - 1); *len = its
+ * full length. */
+int fx_rtc_source(const fx_rtc* r, char* buf, size_t cap, size_t* len);
+/* Milliseconds spent compiling at creation (0: found in the cache). */
+double fx_rtc_compile_ms(const fx_rtc* r);
+/* out[0..n) = the expression over inputs[0..n_inputs) (all of the storage
+ * dtype, 16-byte aligned).  Loads the module on the current device at its
+ * first use; enqueues one kernel on `stream`. */
+int fx_rtc_eval(fx_rtc* r, const void* const* inputs, int32_t n_inputs, int64_t n, void* out,
+                void* stream);
+
 /* ---- batches: thousands of uneven expressions in one launch -------------
  * Every expression of a batch is a compiled tape over vectors.  The batch is
  * cut into fixed-size tiles (the tiles of one expression are consecutive);

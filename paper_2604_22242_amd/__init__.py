@@ -115,6 +115,11 @@ _SIGS = {
     "fx_tape_destroy": (None, [_P]),
     "fx_tape_describe": (_I, [_P, ctypes.POINTER(TapeInfo)]),
     "fx_tape_program": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int32]),
+    "fx_rtc_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, _I, ctypes.POINTER(_P)]),
+    "fx_rtc_destroy": (None, [_P]),
+    "fx_rtc_source": (_I, [_P, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
+    "fx_rtc_compile_ms": (ctypes.c_double, [_P]),
+    "fx_rtc_eval": (_I, [_P, ctypes.POINTER(_P), ctypes.c_int32, _I64, _P, _P]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
@@ -485,6 +490,51 @@ def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stre
     p, nb = _ws(ws)
     return check(lib().fx_tape_eval(tape.handle, dt, arr, len(inputs), _shape(shape), kind,
                                     _ptr(out), p, nb, _cfg(cfg), _stream(stream)))
+
+
+# ---- run-time source mode ----------------------------------------------------------------
+
+
+class Rtc:
+    """An fx_rtc handle: the tree's generated kernel, compiled with hipRTC
+    (or found in the per-process cache) on creation."""
+
+    def __init__(self, nodes, dt=F32):
+        self.handle = ctypes.c_void_p()
+        arr = nodes_array(nodes)
+        check(lib().fx_rtc_create(arr, len(nodes), dt, ctypes.byref(self.handle)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fx_rtc_destroy(self.handle)
+            self.handle = None
+
+    def source(self) -> str:
+        return fx_rtc_source(self)
+
+    def compile_ms(self) -> float:
+        return lib().fx_rtc_compile_ms(self.handle)
+
+    def eval(self, inputs, out, n=None, stream=None):
+        return fx_rtc_eval(self, inputs, out, n, stream)
+
+
+def fx_rtc_create(nodes, dt=F32) -> Rtc:
+    return Rtc(nodes, dt)
+
+
+def fx_rtc_source(r: Rtc) -> str:
+    n = _SZ()
+    check(lib().fx_rtc_source(r.handle, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    check(lib().fx_rtc_source(r.handle, buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def fx_rtc_eval(r: Rtc, inputs, out, n=None, stream=None):
+    n = out.numel() if n is None else n
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    return check(lib().fx_rtc_eval(r.handle, arr, len(inputs), n, _ptr(out), _stream(stream)))
 
 
 # ---- batches ----------------------------------------------------------------------------

@@ -74,7 +74,7 @@ def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool
             if verbose:
                 print("  %-40s %6.1fs" % (os.path.basename(obj), dt), flush=True)
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lhiprtc"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stderr)

@@ -72,6 +72,7 @@ int check_launch(const fx_launch* c) {
 static constexpr int kReduceBlocksPerCU = 2;
 static constexpr int kColsumBlocksPerCU = 8;
 static constexpr int kRowsumWavesPerCU = 8;
+constexpr int kRowsumMinCols = 32;
 
 launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_launch* cfg,
                bool aligned16) {
@@ -90,7 +91,11 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
     L.block = c.block ? c.block : ew ? 512 : 256;
     L.ept = c.ept ? c.ept : ew ? 1 : 2;
     const int64_t tiles = std::max<int64_t>(1, ceil_div(n, (int64_t)L.block * L.ept * vec16));
-    const int64_t want = ew ? tiles : std::min<int64_t>(tiles, cus * kReduceBlocksPerCU);
+    // full reductions: one ticket per block; below 2^24 elements the tickets
+    // of two blocks per CU cost more than the extra bandwidth buys (measured:
+    // 8.0 vs 10.3 us at 2^20), above it two per CU keep HBM busier
+    const int64_t per_cu = n < ((int64_t)1 << 24) ? 1 : kReduceBlocksPerCU;
+    const int64_t want = ew ? tiles : std::min<int64_t>(tiles, cus * per_cu);
     L.split = c.split ? c.split : (int)std::min<int64_t>(want, 1 << 30);
   } else if (kind == FX_R_COLSUM) {
     L.block = c.block ? c.block : elem >= 4 ? 512 : 256;
@@ -110,6 +115,10 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
     const int64_t rblocks = std::max<int64_t>(1, ceil_div(n_rows, (int64_t)L.block * vec16));
     const int64_t target = cus * kRowsumWavesPerCU * 64 / L.block;
     int64_t s = c.split ? c.split : ceil_div(target, rblocks);
+    // a defaulted split keeps at least kRowsumMinCols columns per chunk: the
+    // finish adds `split` partials per row one after another, so thousands of
+    // one-column chunks (a short, wide matrix) cost more than they spread
+    if (!c.split) s = std::min<int64_t>(s, std::max<int64_t>(1, n_cols / kRowsumMinCols));
     s = std::min<int64_t>(s, std::max<int64_t>(1, n_cols));
     L.split = (int)std::max<int64_t>(1, std::min<int64_t>(s, 65535));
   }
