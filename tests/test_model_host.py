@@ -1,0 +1,52 @@
+"""CPU checks of the committed launch-configuration model: its files are
+consistent, and a numpy forward pass over the documented parameter layout
+reproduces the choice reported for the matrix workload."""
+import json
+import os
+
+import numpy as np
+
+from paper_2604_22242_amd import model, tune
+
+HERE = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PATH = os.path.join(HERE, "paper_2604_22242_amd", "launch_model")
+
+
+def _load():
+    meta = json.load(open(PATH + ".json"))
+    p = np.fromfile(PATH + ".bin", np.float32)
+    F, H, heads = meta["n_features"], meta["hidden"], meta["heads"]
+    C = sum(heads)
+    assert p.size == H * F + H + C * H + C
+    W1 = p[:H * F].reshape(H, F)
+    b1 = p[H * F:H * F + H]
+    W2 = p[H * F + H:H * F + H + C * H].reshape(C, H)
+    b2 = p[H * F + H + C * H:]
+    return meta, W1, b1, W2, b2
+
+
+def choose(x):
+    meta, W1, b1, W2, b2 = _load()
+    z = (np.asarray(x, np.float32) - np.array(meta["mean"], np.float32)) / np.array(meta["std"], np.float32)
+    h = np.maximum(W1 @ z + b1, 0)
+    logits = W2 @ h + b2
+    out, o = [], 0
+    for k in meta["heads"]:
+        out.append(int(np.argmax(logits[o:o + k])))
+        o += k
+    return tuple(out)
+
+
+def test_model_files():
+    meta, *_ = _load()
+    assert meta["n_features"] == len(tune.FEATURES) == 25 and meta["hidden"] == 64
+    assert tuple(meta["heads"]) == tune.HEADS and meta["features"] == tune.FEATURES
+    assert all(s > 0 for s in meta["std"])
+
+
+def test_choice_for_the_matrix_workload():
+    import paper_2604_22242_amd as fx
+    info = fx.Tape(model.C2_NODES).info()
+    ch = choose(tune.features(info, "f32", (8192, 8192), None))
+    # the evaluation report's pick for the fused Z: 128 threads, EPT 1, 16 B
+    assert model.config_of(ch, None, "f32") == (128, 1, 16, 0)
