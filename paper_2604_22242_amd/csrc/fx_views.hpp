@@ -12,8 +12,9 @@
 //
 // Evaluation.  A diagonal is a vector, so expressions over diagonals run
 // through the linear skeletons.  Expressions with Sub or Trans leaves run
-// through k_ew2d: one block per (16 * N) x 64 output tile, each thread a
-// vector of N consecutive rows in four columns.  Dense and submatrix leaves
+// through k_ew2d: one block per output tile ((16 * N) x 64 with transposed
+// leaves, (64 * N) x 16 without), each thread a vector of N consecutive rows
+// in four columns.  Dense and submatrix leaves
 // are read straight from HBM (16-byte vectors when every view is aligned);
 // a transposed leaf's source tile is first staged in LDS by the whole block
 // with coalesced reads along the source's columns (column pitch 16 * N + 1
@@ -353,22 +354,31 @@ __device__ __forceinline__ void stage(const Binary<Op, A, B>& e, const tile_ctx<
 // (blockIdx.x: tile row, blockIdx.y: tile column; launching the partner
 // tiles (I, J) and (J, I) side by side, to find a transposed operand's tile in
 // the last-level cache, measured slower on the 10k x 10k expressions.)
+// Tile geometry: with transposed leaves the tile is (16 N) x 64 (square for
+// FP32, the LDS staging tile); without them it is (64 N) x 16, so that each
+// column of every leaf is read in 1 KB-or-longer contiguous runs (square
+// tiles read only 256 B per column of a submatrix, measured slower).
+template <int KT> constexpr int kRowVecs = KT > 0 ? 16 : 64;        // thread rows per tile
+template <int KT> constexpr int kColsPerTile = KT > 0 ? kTileCols : 16;
+
 template <class E, class T, int N>
 __global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, int64_t rows,
                                                       int64_t cols) {
   using C = typename E::ct;
   constexpr int KT = trans_count<E>::value;
+  constexpr int RV = kRowVecs<KT>, CG = kTileThreads / RV, TC = kColsPerTile<KT>;
   __shared__ C lds[KT > 0 ? KT * kTileBuf<N> : 1];
-  const tile_ctx<C, N> x{lds, (int64_t)blockIdx.x * kTileRows<N>, (int64_t)blockIdx.y * kTileCols};
+  const tile_ctx<C, N> x{lds, (int64_t)blockIdx.x * RV * N, (int64_t)blockIdx.y * TC};
   if constexpr (KT > 0) {
+    static_assert(RV * N == kTileRows<N> && TC == kTileCols, "staging tile geometry");
     stage<0, N>(e, x, rows, cols);
     __syncthreads();
   }
-  const int rv = threadIdx.x % 16, cg = threadIdx.x / 16;
+  const int rv = threadIdx.x % RV, cg = threadIdx.x / RV;
   const int64_t r = x.r0 + rv * N;
 #pragma unroll
-  for (int q = 0; q < kTileCols / 16; ++q) {
-    const int64_t c = x.c0 + cg + 16 * q;
+  for (int q = 0; q < TC / CG; ++q) {
+    const int64_t c = x.c0 + cg + CG * q;
     if (c >= cols || r >= rows) continue;
     if (r + N <= rows) {
       store_lanes<N, kNTS>(z, r + c * rows, at2<0, N>(e, r, c, x));
@@ -409,13 +419,14 @@ int eval_views(T* z, const E& e, hipStream_t st) {
   constexpr int NV = 16 / (int)sizeof(T) > 0 ? 16 / (int)sizeof(T) : 1;
   const bool vec = vec_ok(e, NV) && rows % NV == 0 &&
                    reinterpret_cast<uintptr_t>(z) % 16 == 0;
-  const int64_t tc = ceil_div(cols, kTileCols);
+  constexpr int KT = trans_count<E>::value;
+  const int64_t tc = ceil_div(cols, kColsPerTile<KT>);
   if (tc > 65535) return fail(FX_E_UNSUPPORTED, "%lld columns exceed the tile grid", (long long)cols);
   if (vec) {
-    const dim3 grid((unsigned)ceil_div(rows, kTileRows<NV>), (unsigned)tc);
+    const dim3 grid((unsigned)ceil_div(rows, (int64_t)kRowVecs<KT> * NV), (unsigned)tc);
     hipLaunchKernelGGL((k_ew2d<E, T, NV>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
   } else {
-    const dim3 grid((unsigned)ceil_div(rows, kTileRows<1>), (unsigned)tc);
+    const dim3 grid((unsigned)ceil_div(rows, (int64_t)kRowVecs<KT>), (unsigned)tc);
     hipLaunchKernelGGL((k_ew2d<E, T, 1>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
   }
   return hip_check(hipGetLastError(), "k_ew2d launch");
