@@ -388,6 +388,205 @@ __global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, i
   }
 }
 
+// ---- paired tiles: a matrix read both directly and transposed ----------------
+//
+// When an expression over square matrices names a matrix both directly and
+// transposed (expr1: X and X.t()), output tiles (I, J) and (J, I) need the same
+// two tiles of it.  One block then computes both output tiles: it stages tiles
+// (I, J) and (J, I) of every distinct matrix in LDS once (natural layout,
+// column pitch 65) and every leaf reads from there, the direct ones at
+// [c][r] of their own tile, the transposed ones at [r][c] of the partner
+// tile.  Each matrix is read from HBM once.  FP32 (64 x 64 square tiles),
+// whole matrices only, at most kPairMats distinct ones.
+constexpr int kPairMats = 2;
+constexpr int kPairT = 64;            // tile side
+constexpr int kPairPitch = kPairT + 1;
+constexpr int kPairBuf = kPairT * kPairPitch;
+
+template <class E> struct pairable { static constexpr bool value = false; };
+template <class T> struct pairable<Leaf<T>> { static constexpr bool value = true; };
+template <class T> struct pairable<Trans<T>> { static constexpr bool value = true; };
+template <class Op, class A> struct pairable<Unary<Op, A>> : pairable<A> {};
+template <class Op, class A, bool L> struct pairable<Scalar<Op, A, L>> : pairable<A> {};
+template <class Op, class A, class B> struct pairable<Binary<Op, A, B>> {
+  static constexpr bool value = pairable<A>::value && pairable<B>::value;
+};
+template <class E> struct pair_leaves { static constexpr int value = 0; };
+template <class T> struct pair_leaves<Leaf<T>> { static constexpr int value = 1; };
+template <class T> struct pair_leaves<Trans<T>> { static constexpr int value = 1; };
+template <class Op, class A> struct pair_leaves<Unary<Op, A>> : pair_leaves<A> {};
+template <class Op, class A, bool L> struct pair_leaves<Scalar<Op, A, L>> : pair_leaves<A> {};
+template <class Op, class A, class B> struct pair_leaves<Binary<Op, A, B>> {
+  static constexpr int value = pair_leaves<A>::value + pair_leaves<B>::value;
+};
+constexpr int kPairMaxLeaves = 16;
+
+struct pair_tab {
+  uint8_t mid[kPairMaxLeaves];  // leaf (depth-first) -> distinct matrix
+  const float* mat[kPairMats];  // distinct matrices
+  int32_t n_mats;
+};
+
+struct pair_ctx {
+  const float* lds;
+  const uint8_t* mid;
+  int64_t r0, c0;
+  int swap;  // 0: output tile (I, J), 1: its partner (J, I)
+};
+
+// region 2m holds tile (I, J) of matrix m, region 2m + 1 tile (J, I)
+template <int LOFF, class T>
+__device__ __forceinline__ lanes<float, 4> at2p(const Leaf<T>&, int64_t r, int64_t c,
+                                                const pair_ctx& x) {
+  const float* b = x.lds + (2 * x.mid[LOFF] + x.swap) * kPairBuf + (c - x.c0) * kPairPitch + (r - x.r0);
+  lanes<float, 4> v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v.v[j] = b[j];
+  return v;
+}
+template <int LOFF, class T>
+__device__ __forceinline__ lanes<float, 4> at2p(const Trans<T>&, int64_t r, int64_t c,
+                                                const pair_ctx& x) {
+  const float* b = x.lds + (2 * x.mid[LOFF] + 1 - x.swap) * kPairBuf + (r - x.r0) * kPairPitch + (c - x.c0);
+  lanes<float, 4> v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v.v[j] = b[j * kPairPitch];
+  return v;
+}
+template <int LOFF, class Op, class A>
+__device__ __forceinline__ lanes<float, 4> at2p(const Unary<Op, A>& e, int64_t r, int64_t c,
+                                                const pair_ctx& x) {
+  lanes<float, 4> v = at2p<LOFF>(e.a, r, c, x);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v.v[j] = Op::apply(v.v[j]);
+  return v;
+}
+template <int LOFF, class Op, class A, bool L>
+__device__ __forceinline__ lanes<float, 4> at2p(const Scalar<Op, A, L>& e, int64_t r, int64_t c,
+                                                const pair_ctx& x) {
+  lanes<float, 4> v = at2p<LOFF>(e.a, r, c, x);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v.v[j] = e.apply1(v.v[j]);
+  return v;
+}
+template <int LOFF, class Op, class A, class B>
+__device__ __forceinline__ lanes<float, 4> at2p(const Binary<Op, A, B>& e, int64_t r, int64_t c,
+                                                const pair_ctx& x) {
+  lanes<float, 4> u = at2p<LOFF>(e.a, r, c, x);
+  lanes<float, 4> w = at2p<LOFF + pair_leaves<A>::value>(e.b, r, c, x);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) u.v[j] = Op::apply(u.v[j], w.v[j]);
+  return u;
+}
+
+// One block per tile pair I <= J (p enumerates them column by column); n x n
+// FP32 result, n a multiple of 4.
+template <class E>
+__global__ __launch_bounds__(kTileThreads) void k_ew2d_pair(E e, pair_tab tab, float* __restrict__ z,
+                                                           int64_t n) {
+  __shared__ float lds[2 * kPairMats * kPairBuf];
+  const int64_t p = blockIdx.x;
+  int64_t J = (int64_t)((::sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (J * (J + 1) / 2 > p) --J;
+  while ((J + 1) * (J + 2) / 2 <= p) ++J;
+  const int64_t I = p - J * (J + 1) / 2;
+  // stage tiles (I, J) and (J, I) of every matrix: 16-byte loads down the
+  // columns (64 rows = 16 vectors per column); each thread issues all its
+  // loads before the first LDS write
+  constexpr int PER = kPairT * (kPairT / 4) / kTileThreads;  // vectors per thread per tile
+  lanes<float, 4> v[kPairMats][2][PER];
+#pragma unroll
+  for (int m = 0; m < kPairMats; ++m)
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * kTileThreads;
+        const int64_t r = (w ? J : I) * kPairT + (idx % (kPairT / 4)) * 4;
+        const int64_t c = (w ? I : J) * kPairT + idx / (kPairT / 4);
+        if (m < tab.n_mats && r < n && c < n) v[m][w][k] = load_lanes<4, kNT>(tab.mat[m], r + c * n);
+      }
+#pragma unroll
+  for (int m = 0; m < kPairMats; ++m)
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * kTileThreads;
+        const int rl = (idx % (kPairT / 4)) * 4, cl = idx / (kPairT / 4);
+        float* buf = lds + (2 * m + w) * kPairBuf + cl * kPairPitch + rl;
+        if (m < tab.n_mats)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) buf[j] = v[m][w][k].v[j];
+      }
+  __syncthreads();
+  const int rv = threadIdx.x % 16, cg = threadIdx.x / 16;
+  for (int s = 0; s < (I == J ? 1 : 2); ++s) {
+    const pair_ctx x{lds, tab.mid, (s ? J : I) * kPairT, (s ? I : J) * kPairT, s};
+    const int64_t r = x.r0 + rv * 4;
+#pragma unroll
+    for (int q = 0; q < kPairT / 16; ++q) {
+      const int64_t c = x.c0 + cg + 16 * q;
+      if (c < n && r < n) store_lanes<4, kNTS>(z, r + c * n, at2p<0>(e, r, c, x));
+    }
+  }
+}
+
+// Host: the leaves (depth-first) of a pairable expression.
+template <class T> inline void pair_leaf_list(const Leaf<T>& e, const void** p, int64_t* off,
+                                              int64_t* ld, bool* tr, int& k) {
+  p[k] = e.p; off[k] = 0; ld[k] = e.n_rows; tr[k] = false; ++k;
+}
+template <class T> inline void pair_leaf_list(const Trans<T>& e, const void** p, int64_t* off,
+                                              int64_t* ld, bool* tr, int& k) {
+  p[k] = e.p; off[k] = e.off; ld[k] = e.ld; tr[k] = true; ++k;
+}
+template <class Op, class A> inline void pair_leaf_list(const Unary<Op, A>& e, const void** p,
+                                                        int64_t* off, int64_t* ld, bool* tr, int& k) {
+  pair_leaf_list(e.a, p, off, ld, tr, k);
+}
+template <class Op, class A, bool L> inline void pair_leaf_list(const Scalar<Op, A, L>& e,
+                                                                const void** p, int64_t* off,
+                                                                int64_t* ld, bool* tr, int& k) {
+  pair_leaf_list(e.a, p, off, ld, tr, k);
+}
+template <class Op, class A, class B> inline void pair_leaf_list(const Binary<Op, A, B>& e,
+                                                                 const void** p, int64_t* off,
+                                                                 int64_t* ld, bool* tr, int& k) {
+  pair_leaf_list(e.a, p, off, ld, tr, k);
+  pair_leaf_list(e.b, p, off, ld, tr, k);
+}
+
+// Build the pair table if the paired kernel applies: n x n FP32 result,
+// every leaf a whole n x n matrix, at most kPairMats distinct ones, one of
+// them read both ways, 16-byte aligned.
+template <class E> inline bool pair_plan(const E& e, int64_t n, const float* z, pair_tab* tab) {
+  constexpr int L = pair_leaves<E>::value;
+  if (L > kPairMaxLeaves || n % 4 || reinterpret_cast<uintptr_t>(z) % 16) return false;
+  const void* p[kPairMaxLeaves];
+  int64_t off[kPairMaxLeaves], ld[kPairMaxLeaves];
+  bool tr[kPairMaxLeaves];
+  int k = 0;
+  pair_leaf_list(e, p, off, ld, tr, k);
+  bool dir[kPairMats] = {false, false}, trn[kPairMats] = {false, false};
+  tab->n_mats = 0;
+  for (int i = 0; i < L; ++i) {
+    if (off[i] != 0 || ld[i] != n || reinterpret_cast<uintptr_t>(p[i]) % 16) return false;
+    int m = 0;
+    while (m < tab->n_mats && tab->mat[m] != p[i]) ++m;
+    if (m == tab->n_mats) {
+      if (m == kPairMats) return false;
+      tab->mat[m] = static_cast<const float*>(p[i]);
+      ++tab->n_mats;
+    }
+    tab->mid[i] = (uint8_t)m;
+    (tr[i] ? trn : dir)[m] = true;
+  }
+  for (int m = 0; m < tab->n_mats; ++m)
+    if (dir[m] && trn[m]) return true;
+  return false;
+}
+
 // Host: may every dense / submatrix leaf and the output be read N at a time?
 template <class T> inline bool vec_ok(const Leaf<T>& e, int N) {
   return (reinterpret_cast<uintptr_t>(e.p) % (N * sizeof(T))) == 0 && e.n_rows % N == 0;
@@ -420,6 +619,16 @@ int eval_views(T* z, const E& e, hipStream_t st) {
   const bool vec = vec_ok(e, NV) && rows % NV == 0 &&
                    reinterpret_cast<uintptr_t>(z) % 16 == 0;
   constexpr int KT = trans_count<E>::value;
+  if constexpr (KT > 0 && pairable<E>::value && std::is_same_v<T, float> &&
+                std::is_same_v<typename E::ct, float>) {
+    pair_tab tab;
+    if (rows == cols && pair_plan(e, rows, z, &tab)) {
+      const int64_t t = ceil_div(rows, (int64_t)kPairT);
+      hipLaunchKernelGGL((k_ew2d_pair<E>), dim3((unsigned)(t * (t + 1) / 2)), dim3(kTileThreads), 0,
+                         st, e, tab, z, rows);
+      return hip_check(hipGetLastError(), "k_ew2d_pair launch");
+    }
+  }
   const int64_t tc = ceil_div(cols, kColsPerTile<KT>);
   if (tc > 65535) return fail(FX_E_UNSUPPORTED, "%lld columns exceed the tile grid", (long long)cols);
   if (vec) {
