@@ -164,3 +164,53 @@ def test_training_reduces_loss_on_separable_data():
     m.forward(Xd, None, choice)
     torch.cuda.synchronize()
     assert (choice.cpu().numpy() == y).all(axis=1).mean() > 0.9
+
+
+def test_committed_model_drives_tapes():
+    """The trained model shipped with the package loads, its inference kernel
+    and host twin agree on its own weights, and tapes launched with its
+    picks (held-out items of the tuning set, shrunk to test sizes) match the
+    oracle."""
+    torch, fx = need_gpu()
+    import os
+    import oracle
+    from gpu_util import assert_close, empty, from_dev, oracle_expr, tree_inputs
+    from paper_2604_22242_amd import model, tune
+    from synth import trees
+    path = os.path.join(os.path.dirname(fx.LIB_PATH), "launch_model")
+    m = model.load(path)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    feats, items = [], []
+    for i in range(40):
+        it = trees.tuning_item(6, i)
+        red = it["reduce"]
+        shape = (257, 131) if red in ("colsum", "rowsum") else (33331, 1)
+        info = fx.Tape(it["nodes"]).info()
+        feats.append(tune.features(info, it["dtype"], it["shape"], red))
+        items.append((it, shape, red))
+    X = torch.tensor(np.array(feats, np.float32)).cuda()
+    choice = torch.empty(len(feats), len(tune.HEADS), dtype=torch.int32, device="cuda")
+    m.forward(X, None, choice)
+    torch.cuda.synchronize()
+    ch = choice.cpu().numpy()
+    for (it, shape, red), f, c in zip(items, feats, ch):
+        assert m.choose(f) == list(c)
+        cfg = model.config_of(tuple(c), red, it["dtype"], cus)
+        dt = it["dtype"]
+        dcode = fx.F32 if dt == "f32" else fx.BF16
+        n = shape[0] * shape[1]
+        host, dev = tree_inputs(6, it["id"], it["n_inputs"], n, dt)
+        kind = tune.KIND[red]
+        if kind == 0:
+            out, od = empty(n, dt), dt
+        elif red in ("accu", "norm"):
+            out, od = torch.zeros(1, dtype=torch.float64, device="cuda"), "f64"
+        else:
+            out, od = empty(shape[1] if red == "colsum" else shape[0], "f32"), "f32"
+        ws = fx.workspace(kind, dcode, shape, cfg) if kind else None
+        fx.fx_tape_eval(fx.Tape(it["nodes"]), dev, out, shape, kind, ws, cfg=cfg, dt=dcode)
+        torch.cuda.synchronize()
+        v, mu = oracle.evaluate(oracle_expr(it["nodes"]), host, dt, shape=shape, reduce=red)
+        half = dt if (kind == 0 and dt == "bf16") else None
+        assert_close(from_dev(out, od), v, mu, dt, "model-picked %s item %d" % (cfg, it["id"]),
+                     out_dtype=half)
