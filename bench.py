@@ -282,8 +282,9 @@ def paper_suite_detail(fx, torch, stream, reps):
 def modes_detail(fx, torch, stream, reps):
     """One expression three ways: compile-time template (the fused kernel),
     run-time tape (interpreter) and run-time source (hipRTC-compiled at first
-    use).  The matrix workload's Z over 2^26 FP32 elements, and the deepest of
-    the first 200 generated tuning trees (depth <= 8) over 2^26 elements."""
+    use).  The matrix workload's Z and its column sums over 2^26 FP32
+    elements, and the deepest of the first 200 generated tuning trees
+    (depth <= 8) over 2^26 elements."""
     import synth
     from synth import trees
     from paper_2604_22242_amd.model import C2_NODES
@@ -300,6 +301,19 @@ def modes_detail(fx, torch, stream, reps):
             tape, ins[:3], Z, (n, 1), stream=stream), reps), 4),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:3], Z, stream=stream), reps), 4),
+        "hiprtc_compile_ms": round(r.compile_ms(), 1)}
+    cs = torch.empty(COLS, device="cuda")
+    shape = (ROWS, COLS)
+    ws = fx.workspace(fx.R_COLSUM, fx.F32, shape)
+    r = fx.Rtc(C2_NODES, fx.F32, fx.R_COLSUM)
+    tape = fx.Tape(C2_NODES)
+    out["c2_colsum"] = {
+        "compile_time_ms": round(event_ms(torch, stream, lambda: fx.fx_c2_colsum(
+            *ins[:3], cs, shape, ws, stream=stream), reps), 4),
+        "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
+            tape, ins[:3], cs, shape, fx.R_COLSUM, ws, stream=stream), reps), 4),
+        "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
+            ins[:3], cs, shape, ws, stream=stream), reps), 4),
         "hiprtc_compile_ms": round(r.compile_ms(), 1)}
     best = max((trees.tuning_item(5, i) for i in range(200)),
                key=lambda it: fx.Tape(it["nodes"]).info()["n_instructions"])

@@ -355,28 +355,41 @@ int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
 /* ---- run-time source mode -------------------------------------------------
  * The paper's own mechanism (Sec. 3): the kernel source of an expression is
  * generated, compiled through the driver at first use and reused.  Here a
- * tree (the fx_node list of the tapes) becomes the HIP source of one fused
- * element-wise kernel, compiled with hipRTC for gfx950 with the library's
- * flags and cached per process by its text; the compiled kernel reads each
- * input once and writes once, like a compile-time expression, without the
- * interpreter's per-instruction cost.  FP32 and FP64 storage. */
+ * tree (the fx_node list of the tapes) and a result kind become the HIP
+ * source of one fused kernel, compiled with hipRTC for gfx950 with the
+ * library's flags and cached per process by its text.  The compiled kernel
+ * reads each input once (and writes once, element-wise), like a
+ * compile-time expression, without the interpreter's per-instruction cost;
+ * its reductions follow the fused ones (compensated per-thread sums, FP64
+ * block and cross-block combine, single-pass finish).  FP32, FP64, BF16 and
+ * FP16 storage; the launch configuration is the library default of the kind
+ * and storage type. */
 typedef struct fx_rtc fx_rtc;
 
 /* Generate and compile (or find in the cache) the kernel of nodes[0..n_nodes)
- * for storage dtype dt.  Synchronous; needs no device.  Compilation errors
- * give FX_E_HIP with the compiler log in fx_last_error. */
-int fx_rtc_create(const fx_node* nodes, int32_t n_nodes, fx_dtype dt, fx_rtc** out);
+ * for storage dtype dt and result kind (0: element-wise; FX_R_ACCU,
+ * FX_R_NORM, FX_R_COLSUM, FX_R_ROWSUM).  Synchronous; needs no device.
+ * Compilation errors give FX_E_HIP with the compiler log in fx_last_error;
+ * another dtype gives FX_E_DTYPE, another kind FX_E_ARG. */
+int fx_rtc_create(const fx_node* nodes, int32_t n_nodes, fx_dtype dt, int kind, fx_rtc** out);
 void fx_rtc_destroy(fx_rtc* r);
 /* The generated source (NUL-terminated, truncated to cap - 1); *len = its
  * full length. */
 int fx_rtc_source(const fx_rtc* r, char* buf, size_t cap, size_t* len);
 /* Milliseconds spent compiling at creation (0: found in the cache). */
 double fx_rtc_compile_ms(const fx_rtc* r);
-/* out[0..n) = the expression over inputs[0..n_inputs) (all of the storage
- * dtype, 16-byte aligned).  Loads the module on the current device at its
- * first use; enqueues one kernel on `stream`. */
-int fx_rtc_eval(fx_rtc* r, const void* const* inputs, int32_t n_inputs, int64_t n, void* out,
-                void* stream);
+/* Evaluate r over inputs[0..n_inputs) (n_inputs >= the tree's inputs, all of
+ * the storage dtype and column-major shape `shape`, 16-byte aligned).  Kind
+ * 0: out has the storage dtype and shape's size (16-byte aligned; exact
+ * aliasing with an input is allowed); FX_R_ACCU / FX_R_NORM: one double;
+ * FX_R_COLSUM / FX_R_ROWSUM: n_cols / n_rows values of the accumulator dtype
+ * (double for FP64 storage, float otherwise).  ws as for the fused
+ * reductions: fx_workspace_bytes(kind, dt, shape, NULL) bytes, zeroed once.
+ * Loads the module on the current device at its first use; enqueues one
+ * kernel on `stream`.  An empty result is a no-op; accu and norm of an empty
+ * shape write 0, dimension sums over an empty dimension write zeros. */
+int fx_rtc_eval(fx_rtc* r, const void* const* inputs, int32_t n_inputs, fx_shape shape, void* out,
+                void* ws, size_t ws_bytes, void* stream);
 
 /* ---- batches: thousands of uneven expressions in one launch -------------
  * Every expression of a batch is a compiled tape over vectors.  The batch is

@@ -115,11 +115,11 @@ _SIGS = {
     "fx_tape_destroy": (None, [_P]),
     "fx_tape_describe": (_I, [_P, ctypes.POINTER(TapeInfo)]),
     "fx_tape_program": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int32]),
-    "fx_rtc_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, _I, ctypes.POINTER(_P)]),
+    "fx_rtc_create": (_I, [ctypes.POINTER(Node), ctypes.c_int32, _I, _I, ctypes.POINTER(_P)]),
     "fx_rtc_destroy": (None, [_P]),
     "fx_rtc_source": (_I, [_P, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "fx_rtc_compile_ms": (ctypes.c_double, [_P]),
-    "fx_rtc_eval": (_I, [_P, ctypes.POINTER(_P), ctypes.c_int32, _I64, _P, _P]),
+    "fx_rtc_eval": (_I, [_P, ctypes.POINTER(_P), ctypes.c_int32, Shape, _P, _P, _SZ, _P]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
@@ -496,13 +496,15 @@ def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stre
 
 
 class Rtc:
-    """An fx_rtc handle: the tree's generated kernel, compiled with hipRTC
-    (or found in the per-process cache) on creation."""
+    """An fx_rtc handle: the generated kernel of a tree and result kind
+    (0: element-wise, or R_ACCU / R_NORM / R_COLSUM / R_ROWSUM), compiled
+    with hipRTC (or found in the per-process cache) on creation."""
 
-    def __init__(self, nodes, dt=F32):
+    def __init__(self, nodes, dt=F32, kind=0):
         self.handle = ctypes.c_void_p()
+        self.kind = kind
         arr = nodes_array(nodes)
-        check(lib().fx_rtc_create(arr, len(nodes), dt, ctypes.byref(self.handle)))
+        check(lib().fx_rtc_create(arr, len(nodes), dt, kind, ctypes.byref(self.handle)))
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -515,12 +517,12 @@ class Rtc:
     def compile_ms(self) -> float:
         return lib().fx_rtc_compile_ms(self.handle)
 
-    def eval(self, inputs, out, n=None, stream=None):
-        return fx_rtc_eval(self, inputs, out, n, stream)
+    def eval(self, inputs, out, shape=None, ws=None, stream=None):
+        return fx_rtc_eval(self, inputs, out, shape, ws, stream)
 
 
-def fx_rtc_create(nodes, dt=F32) -> Rtc:
-    return Rtc(nodes, dt)
+def fx_rtc_create(nodes, dt=F32, kind=0) -> Rtc:
+    return Rtc(nodes, dt, kind)
 
 
 def fx_rtc_source(r: Rtc) -> str:
@@ -531,10 +533,16 @@ def fx_rtc_source(r: Rtc) -> str:
     return buf.value.decode()
 
 
-def fx_rtc_eval(r: Rtc, inputs, out, n=None, stream=None):
-    n = out.numel() if n is None else n
+def fx_rtc_eval(r: Rtc, inputs, out, shape=None, ws=None, stream=None):
+    """shape defaults to (out.numel(), 1) for element-wise kernels."""
+    if shape is None:
+        if r.kind != 0:
+            raise ValueError("a reduction needs the inputs' shape")
+        shape = (out.numel(), 1)
     arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
-    return check(lib().fx_rtc_eval(r.handle, arr, len(inputs), n, _ptr(out), _stream(stream)))
+    p, nb = _ws(ws)
+    return check(lib().fx_rtc_eval(r.handle, arr, len(inputs), _shape(shape), _ptr(out), p, nb,
+                                   _stream(stream)))
 
 
 # ---- batches ----------------------------------------------------------------------------

@@ -128,15 +128,17 @@ struct fx_batch {
   bool small_slots;  // every program fits the 8-slot file
 };
 
+// Release paths cannot report errors: a failure here only means the context
+// is already gone.
 static void batch_free(fx_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  hipFree(b->d_descs);
-  hipFree(b->d_progs);
-  hipFree(b->d_tiles);
-  hipFree(b->d_partials);
-  hipFree(b->d_counters);
-  hipFree(b->d_ws);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  (void)hipFree(b->d_descs);
+  (void)hipFree(b->d_progs);
+  (void)hipFree(b->d_tiles);
+  (void)hipFree(b->d_partials);
+  (void)hipFree(b->d_counters);
+  (void)hipFree(b->d_ws);
 }
 
 static int elem_of(fx_dtype dt) {
@@ -315,13 +317,13 @@ int fx_batch_graph(fx_batch* b, void* stream) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (rc != FX_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     if (int rc2 = hip_check(e, "hipStreamEndCapture")) return rc2;
     hipGraphExec_t x = nullptr;
     if (int rc3 = hip_check(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "hipGraphInstantiate")) {
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       return rc3;
     }
     b->graph = g;
@@ -359,8 +361,9 @@ int fx_batch_describe(const fx_batch* b, fx_batch_info* out) {
 
 void fx_batch_destroy(fx_batch* b) {
   if (!b) return;
-  if (b->last_stream) hipStreamSynchronize(b->last_stream);
-  else hipDeviceSynchronize();
+  // queued work may still use the buffers; a destroy cannot report errors
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  else (void)hipDeviceSynchronize();
   batch_free(b);
   delete b;
 }

@@ -178,18 +178,20 @@ struct fx_model {
   std::vector<float> hP, hMean, hStd;  // host twin for single queries
 };
 
+// Release paths cannot report errors: a failed hipFree here only means the
+// context is already gone.
 static void model_free(fx_model* m) {
-  hipFree(m->dP);
-  hipFree(m->dM);
-  hipFree(m->dV);
-  hipFree(m->dMean);
-  hipFree(m->dStd);
-  hipFree(m->scratch);
+  (void)hipFree(m->dP);
+  (void)hipFree(m->dM);
+  (void)hipFree(m->dV);
+  (void)hipFree(m->dMean);
+  (void)hipFree(m->dStd);
+  (void)hipFree(m->scratch);
 }
 
 static int ensure_scratch(fx_model* m, int B) {
   if (B <= m->cap) return FX_OK;
-  hipFree(m->scratch);
+  (void)hipFree(m->scratch);
   m->scratch = nullptr;
   const mlp_dims& d = m->d;
   const size_t per_row = (size_t)d.F + 2 * d.H + d.C + 1;
@@ -373,7 +375,7 @@ int fx_model_choose(const fx_model* m, const float* x, int32_t* choice) {
 
 void fx_model_destroy(fx_model* m) {
   if (!m) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // queued work may still use the buffers
   model_free(m);
   delete m;
 }

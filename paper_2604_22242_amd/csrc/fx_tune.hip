@@ -22,7 +22,7 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
   std::vector<hipEvent_t> ev(2 * reps, nullptr);
   for (auto& e : ev)
     if (int rc = hip_check(hipEventCreate(&e), "hipEventCreate")) {
-      for (auto& x : ev) if (x) hipEventDestroy(x);
+      for (auto& x : ev) if (x) (void)hipEventDestroy(x);
       return rc;
     }
   int status = FX_OK;
@@ -39,9 +39,9 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
     if (rc != FX_OK) { status = rc; break; }
     for (int w = 1; w < warmup && status == FX_OK; ++w) status = run();
     for (int r = 0; r < reps && status == FX_OK; ++r) {
-      hipEventRecord(ev[2 * r], st);
-      status = run();
-      hipEventRecord(ev[2 * r + 1], st);
+      status = hip_check(hipEventRecord(ev[2 * r], st), "hipEventRecord");
+      if (status == FX_OK) status = run();
+      if (status == FX_OK) status = hip_check(hipEventRecord(ev[2 * r + 1], st), "hipEventRecord");
     }
     if (status != FX_OK) break;
     if ((status = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize")) != FX_OK) break;
@@ -51,6 +51,6 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
       row[r] = m;
     }
   }
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   return status;
 }
