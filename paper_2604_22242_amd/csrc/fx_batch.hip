@@ -71,19 +71,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
         if (v0 - threadIdx.x + step <= nvec) {
           lanes<C, N> r[EPT];
           eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
-#pragma unroll
-          for (int k = 0; k < EPT; ++k)
-#pragma unroll
-            for (int j = 0; j < N; ++j) acc.add(r[k].v[j]);
+          acc.add(tile_sum<map_id, N, EPT>(r));
         } else {
 #pragma unroll
           for (int k = 0; k < EPT; ++k) {
             const int64_t v = v0 + k * blockDim.x;
-            if (v < nvec) {
-              lanes<C, N> r = x.template at_vec<N, kNT>(i0 + v * N);
-#pragma unroll
-              for (int j = 0; j < N; ++j) acc.add(r.v[j]);
-            }
+            if (v < nvec) acc.add(lane_sum<map_id, N>(x.template at_vec<N, kNT>(i0 + v * N)));
           }
         }
       }

@@ -102,7 +102,11 @@ __device__ __forceinline__ void store_lanes(T* __restrict__ p, int64_t i, const 
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
 
+// `part` is the type in which a thread may pre-add a few of its terms
+// before handing their sum to add() (see tile_sum): the compute type for
+// floating point, u64 for u32 so that no pre-added sum wraps.
 template <class C> struct accum {
+  using part = C;
   C s = 0, c = 0;
   __device__ __forceinline__ void add(C t) {
 #pragma clang fp contract(off)
@@ -114,10 +118,25 @@ template <class C> struct accum {
   __device__ __forceinline__ double value() const { return (double)s + (double)c; }
 };
 template <> struct accum<uint32_t> {
+  using part = uint64_t;
   uint64_t s = 0;
-  __device__ __forceinline__ void add(uint32_t t) { s += t; }
+  __device__ __forceinline__ void add(uint64_t t) { s += t; }
   __device__ __forceinline__ uint64_t value() const { return s; }
 };
+
+// Sum of K values as a balanced pairwise tree (v is overwritten).  Each
+// term goes through at most ceil(log2 K) roundings, so a thread that
+// pre-adds its K values of a tile this way and hands the sum to the
+// compensated accumulator keeps the error within the sum's bound (a thread
+// never holds more terms than the whole reduction) at one compensated add
+// per tile instead of one per element.
+template <int K, class P> __device__ __forceinline__ P tree_sum(P (&v)[K]) {
+#pragma unroll
+  for (int w = 1; w < K; w *= 2)
+#pragma unroll
+    for (int i = 0; i + w < K; i += 2 * w) v[i] += v[i + w];
+  return v[0];
+}
 
 // Combination type above the thread: FP64 for floating point, u64 for u32.
 template <class C> struct wide { using type = double; };

@@ -83,7 +83,7 @@ template <class T> struct Leaf : expr_tag {
   static constexpr int kLeaves = 1;
   template <int OFF, int N, bool NT, class R>
   __device__ __forceinline__ void gather(R* regs, const uint8_t* alias, int64_t i) const {
-    if (alias[OFF] == OFF) regs[OFF] = load_lanes<N, NT>(p, i);
+    if (!alias || alias[OFF] == OFF) regs[OFF] = load_lanes<N, NT>(p, i);
   }
   template <int OFF, int N, bool NT, class R>
   __device__ __forceinline__ lanes<ct, N> at_regs(const R* regs, int64_t) const {
@@ -344,8 +344,9 @@ template <class T, int K> struct SumN : expr_tag {
 // compile time by the traversal, so no register is indexed at run time.
 // The loads sit behind uniform branches, which makes the compiler wait for
 // all of them before any arithmetic; the drivers therefore take Fused<E>
-// only when some leaf does repeat, and the plain kernel (whose waits follow
-// the loads one by one) otherwise.
+// only when some leaf does repeat.  Without repeats the same two phases run
+// with no alias table (a null `alias`): every register leaf is loaded
+// unconditionally, so the waits follow the loads one by one.
 constexpr int kMaxFusedLeaves = 16;
 
 template <class E, class = void> struct leaves_of { static constexpr int value = 0; };

@@ -51,14 +51,50 @@ struct map_sq {
   __device__ static double finish(double s) { return ::sqrt(s); }
 };
 
+// The map M of a thread's EPT x N values of one tile, pre-added as a
+// pairwise tree in the accumulator's part type.
+template <class M, int N, int EPT, class C>
+__device__ __forceinline__ typename accum<C>::part tile_sum(const lanes<C, N> (&r)[EPT]) {
+  using P = typename accum<C>::part;
+  P v[EPT * N];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k)
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[k * N + j] = static_cast<P>(M::f(r[k].v[j]));
+  return tree_sum<EPT * N>(v);
+}
+template <class M, int N, class C>
+__device__ __forceinline__ typename accum<C>::part lane_sum(const lanes<C, N>& r) {
+  using P = typename accum<C>::part;
+  P v[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = static_cast<P>(M::f(r.v[j]));
+  return tree_sum<N>(v);
+}
+
 // EPT vectors of N elements at base, base + stride, ...: every leaf's loads
-// are issued before any arithmetic.  Expression types with their own
-// evaluation strategy (the run-time tape) overload this.
+// are issued before any arithmetic (two phases: the register leaves of all
+// EPT vectors, then the tree from registers, with a scheduling barrier
+// between them; left to itself the scheduler may hold a vector's loads back
+// until the previous one has arrived when little arithmetic follows).
+// Expression types with their own evaluation strategy (the run-time tape)
+// overload this.
 template <int N, int EPT, class E>
 __device__ __forceinline__ void eval_tile(const E& e, int64_t base, int64_t stride,
                                           lanes<typename E::ct, N> (&r)[EPT]) {
+  constexpr int L = leaves_of<E>::value;
+  if constexpr (L >= 1 && L <= kMaxFusedLeaves) {
+    lanes<typename E::ct, N> regs[EPT][L];
+    const uint8_t* no_alias = nullptr;
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(base + k * stride);
+    for (int k = 0; k < EPT; ++k) e.template gather<0, N, kNT>(regs[k], no_alias, base + k * stride);
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) r[k] = e.template at_regs<0, N, kNT>(regs[k], base + k * stride);
+  } else {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) r[k] = e.template at_vec<N, kNT>(base + k * stride);
+  }
 }
 
 // Fused<E>: the loads of all EPT vectors first, then the arithmetic.
@@ -125,19 +161,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_full(E e, int64_t n, typename wid
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, v0 * N, (int64_t)blockDim.x * N, r);
-#pragma unroll
-      for (int k = 0; k < EPT; ++k)
-#pragma unroll
-        for (int j = 0; j < N; ++j) acc.add(M::f(r[k].v[j]));
+      acc.add(tile_sum<M, N, EPT>(r));
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int64_t v = v0 + k * blockDim.x;
-        if (v < nv) {
-          lanes<C, N> r = e.template at_vec<N, kNT>(v * N);
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc.add(M::f(r.v[j]));
-        }
+        if (v < nv) acc.add(lane_sum<M, N>(e.template at_vec<N, kNT>(v * N)));
       }
     }
   }
@@ -189,19 +218,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_colsum(E e, int64_t n_rows, int s
     if (t0 + tile <= nv) {
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, base + v0 * N, (int64_t)blockDim.x * N, r);
-#pragma unroll
-      for (int k = 0; k < EPT; ++k)
-#pragma unroll
-        for (int j = 0; j < N; ++j) acc.add(r[k].v[j]);
+      acc.add(tile_sum<map_id, N, EPT>(r));
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int64_t v = v0 + k * blockDim.x;
-        if (v < nv) {
-          lanes<C, N> r = e.template at_vec<N, kNT>(base + v * N);
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc.add(r.v[j]);
-        }
+        if (v < nv) acc.add(lane_sum<map_id, N>(e.template at_vec<N, kNT>(base + v * N)));
       }
     }
   }
@@ -259,9 +281,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_rowsum(E e, int64_t n_rows, int64
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, r0 + c * n_rows, n_rows, r);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k)
+      for (int j = 0; j < N; ++j) {  // row j's EPT columns, pre-added
+        typename accum<C>::part v[EPT];
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc[j].add(r[k].v[j]);
+        for (int k = 0; k < EPT; ++k) v[k] = r[k].v[j];
+        acc[j].add(tree_sum<EPT>(v));
+      }
     }
     for (; c < c1; ++c) {
       lanes<C, N> r = e.template at_vec<N, kNT>(r0 + c * n_rows);

@@ -172,6 +172,7 @@ extern "C" __global__ __launch_bounds__(FX_BLOCK) void fx_rtc_ew(FX_PARAMS, st_t
       ct_t r[FX_EPT][FX_N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_load<FX_N>(FX_ARGS, (v0 + (long)k * FX_BLOCK) * FX_N, raw[k]);
+      __builtin_amdgcn_sched_barrier(0);  // every load ahead of the arithmetic
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_eval<FX_N>(raw[k], r[k]);
 #pragma unroll
@@ -195,8 +196,8 @@ extern "C" __global__ __launch_bounds__(FX_BLOCK) void fx_rtc_ew(FX_PARAMS, st_t
 }
 )";
 
-// Sums: Neumaier's compensated per-thread sum in the compute type, handed
-// upward in FP64; the block sum is a wave64 butterfly and then the waves'
+// Sums: Neumaier's compensated per-thread sum in the compute type, of the
+// pairwise pre-added values of each tile, handed upward in FP64; the block sum is a wave64 butterfly and then the waves'
 // results in order; partials are published with agent-scope stores and the
 // block that draws the last ticket of an agent-scope counter adds them in
 // index order after one acquire, then clears the counter.
@@ -214,6 +215,15 @@ __device__ __forceinline__ void fx_add(fx_acc& a, ct_t t) {
   a.s = u;
 }
 __device__ __forceinline__ double fx_value(const fx_acc& a) { return (double)a.s + (double)a.c; }
+// a thread's K values of one tile, pre-added as a balanced pairwise tree and
+// handed to the compensated sum as one term
+template <int K> __device__ __forceinline__ ct_t fx_tree(ct_t (&v)[K]) {
+#pragma unroll
+  for (int w = 1; w < K; w *= 2)
+#pragma unroll
+    for (int i = 0; i + w < K; i += 2 * w) v[i] += v[i + w];
+  return v[0];
+}
 
 __device__ __forceinline__ double fx_block_sum(double v, double* lds) {
 #pragma unroll
@@ -262,12 +272,15 @@ extern "C" __global__ __launch_bounds__(FX_BLOCK) void fx_rtc_full(FX_PARAMS, lo
       ct_t r[FX_EPT][FX_N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_load<FX_N>(FX_ARGS, (v0 + (long)k * FX_BLOCK) * FX_N, raw[k]);
+      __builtin_amdgcn_sched_barrier(0);  // every load ahead of the arithmetic
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_eval<FX_N>(raw[k], r[k]);
+      ct_t v[FX_EPT * FX_N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k)
 #pragma unroll
-        for (int j = 0; j < FX_N; ++j) fx_add(acc, FX_MAP(r[k][j]));
+        for (int j = 0; j < FX_N; ++j) v[k * FX_N + j] = FX_MAP(r[k][j]);
+      fx_add(acc, fx_tree<FX_EPT * FX_N>(v));
     } else {
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) {
@@ -278,7 +291,8 @@ extern "C" __global__ __launch_bounds__(FX_BLOCK) void fx_rtc_full(FX_PARAMS, lo
           fx_load<FX_N>(FX_ARGS, v * FX_N, raw);
           fx_eval<FX_N>(raw, r);
 #pragma unroll
-          for (int j = 0; j < FX_N; ++j) fx_add(acc, FX_MAP(r[j]));
+          for (int j = 0; j < FX_N; ++j) r[j] = FX_MAP(r[j]);
+          fx_add(acc, fx_tree<FX_N>(r));
         }
       }
     }
@@ -328,12 +342,15 @@ __device__ __forceinline__ void fx_colsum(FX_PARAMS, long n_rows, int split, lon
       ct_t r[FX_EPT][N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_load<N>(FX_ARGS, base + (v0 + (long)k * FX_BLOCK) * N, raw[k]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_eval<N>(raw[k], r[k]);
+      ct_t v[FX_EPT * N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k)
 #pragma unroll
-        for (int j = 0; j < N; ++j) fx_add(acc, r[k][j]);
+        for (int j = 0; j < N; ++j) v[k * N + j] = r[k][j];
+      fx_add(acc, fx_tree<FX_EPT * N>(v));
     } else {
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) {
@@ -343,8 +360,7 @@ __device__ __forceinline__ void fx_colsum(FX_PARAMS, long n_rows, int split, lon
           ct_t r[N];
           fx_load<N>(FX_ARGS, base + v * N, raw);
           fx_eval<N>(raw, r);
-#pragma unroll
-          for (int j = 0; j < N; ++j) fx_add(acc, r[j]);
+          fx_add(acc, fx_tree<N>(r));
         }
       }
     }
@@ -398,12 +414,16 @@ __device__ __forceinline__ void fx_rowsum(FX_PARAMS, long n_rows, long n_cols, i
       ct_t r[FX_EPT][N];
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_load<N>(FX_ARGS, r0 + (c + k) * n_rows, raw[k]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k = 0; k < FX_EPT; ++k) fx_eval<N>(raw[k], r[k]);
 #pragma unroll
-      for (int k = 0; k < FX_EPT; ++k)
+      for (int j = 0; j < N; ++j) {  // row j's FX_EPT columns, pre-added
+        ct_t v[FX_EPT];
 #pragma unroll
-        for (int j = 0; j < N; ++j) fx_add(acc[j], r[k][j]);
+        for (int k = 0; k < FX_EPT; ++k) v[k] = r[k][j];
+        fx_add(acc[j], fx_tree<FX_EPT>(v));
+      }
     }
     for (; c < c1; ++c) {
       fx_raw<N> raw;
