@@ -360,7 +360,7 @@ def paper_views_detail(fx, torch, stream, reps):
     return out
 
 
-PROFILE = os.path.join(ROOT, "profiles", "c2_fp32_8192_fused.md")
+PROFILE = os.path.join(ROOT, "profiles", "c2_8192_fused_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_22242_amd", "csrc", f)
                   for f in ("fx_core.hpp", "fx_expr.hpp", "fx_kernels.hpp", "fx_fused_c2.hip",
                             "fx_fused_c2sum.hip", "fx_fused_xy.hip")]
@@ -428,8 +428,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the fused FP32 steps")
     ap.add_argument("--profile", action="store_true",
-                    help="fused FP32 steps plus one 1 GiB copy (the known-size kernel that "
-                         "scales hardware byte counters); no CPU baseline")
+                    help="fused FP32 steps, then the same steps with BF16 storage, plus one "
+                         "1 GiB copy (the known-size kernel that scales hardware byte "
+                         "counters); no CPU baseline")
     a = ap.parse_args()
     if a.profile:
         a.no_extra = a.no_cpu = True
@@ -494,6 +495,13 @@ def main():
         torch.cuda.empty_cache()
 
     if a.profile:
+        del wl
+        torch.cuda.empty_cache()
+        log("bench: fused BF16 storage steps")
+        wb = Workload(fx, torch, "bf16", ROWS, COLS)
+        time_steps(torch, wb.fused, a.steps, a.warmup, stream)
+        del wb
+        torch.cuda.empty_cache()
         log("bench: 1 GiB reference copy")
         copy_ceiling(fx, torch, stream, nbytes=1 << 30, reps=1)
 
