@@ -190,7 +190,9 @@ def et_check(m: Model, cus: int, rows=8192, cols=8192, reps=5):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", nargs="+", required=True)
+    ap.add_argument("--train", nargs="+", default=[])
+    ap.add_argument("--model", default=None,
+                    help="evaluate this saved model (path without suffix) instead of training")
     ap.add_argument("--heldout", nargs="*", default=[])
     ap.add_argument("--out", default=None)
     ap.add_argument("--epochs", type=int, default=400)
@@ -198,14 +200,20 @@ def main(argv=None):
     ap.add_argument("--et-check", action="store_true",
                     help="also apply the model to the compile-time matrix-workload kernels")
     a = ap.parse_args(argv)
+    if bool(a.train) == bool(a.model):
+        ap.error("give either --train databases or a saved --model")
     tr = [r for p in a.train for r in load_db(p).values()]
     ho = [r for p in a.heldout for r in load_db(p).values()]
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    t0 = time.time()
-    m, curve = train(tr, epochs=a.epochs, verbose=True)
-    rep = {"train_records": len(tr), "train_seconds": round(time.time() - t0, 1),
-           "loss_curve": curve, "train_fit": evaluate(m, tr, cus)}
+    if a.model:
+        m = load(a.model)
+        rep = {"model": a.model}
+    else:
+        t0 = time.time()
+        m, curve = train(tr, epochs=a.epochs, verbose=True)
+        rep = {"train_records": len(tr), "train_seconds": round(time.time() - t0, 1),
+               "loss_curve": curve, "train_fit": evaluate(m, tr, cus)}
     if ho:
         rep["heldout"] = evaluate(m, ho, cus)
     if a.et_check:
