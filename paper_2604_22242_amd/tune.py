@@ -179,6 +179,63 @@ def retime_default(rec, pool, warmup=2, reps=5):
     return out
 
 
+def noise_summary(pairs) -> dict:
+    """Timing noise from (first, second) measurements of the same cells.
+    With independent errors of relative spread c in each, the relative
+    difference d = t2/t1 - 1 spreads by about c * sqrt(2); the robust
+    estimate uses the median absolute deviation (x 1.4826 for a normal
+    spread)."""
+    import numpy as np
+    t1 = np.array([a for a, _ in pairs], float)
+    t2 = np.array([b for _, b in pairs], float)
+    ok = np.isfinite(t1) & np.isfinite(t2) & (t1 > 0)
+    d = t2[ok] / t1[ok] - 1.0
+    if d.size == 0:
+        return {"cells": 0}
+    mad = float(np.median(np.abs(d - np.median(d))))
+    return {"cells": int(d.size),
+            "median_ratio": round(float(np.median(d)) + 1.0, 4),
+            "cv_estimate": round(1.4826 * mad / math.sqrt(2.0), 4),
+            "within_2pct": round(float(np.mean(np.abs(d) <= 0.02)), 4),
+            "within_5pct": round(float(np.mean(np.abs(d) <= 0.05)), 4)}
+
+
+def retime_noise(recs, pool, frac=0.01, seed=0, warmup=2, reps=5, progress=None):
+    """Re-time every record's argmin and a random `frac` of its other grid
+    cells (seeded), against the times stored at collection.  The argmin is
+    the least of many noisy times, so its re-time also shows how much of a
+    winning margin is luck."""
+    import random
+    from synth import trees
+    rng = random.Random(seed)
+    best_pairs, sample_pairs, still_best = [], [], []
+    t0 = time.time()
+    for k, rec in enumerate(recs):
+        item = trees.tuning_item(rec["seed"], rec["id"])
+        assert key_of(item) == rec["key"], "record does not match its generated item"
+        cfgs = record_grid(rec)
+        cells = [rec["best"]] + [i for i in range(len(cfgs) - 1)
+                                 if i != rec["best"] and rec["ms"][i] is not None
+                                 and rec["ms"][i] == rec["ms"][i] and rng.random() < frac]
+        tape = Tape(item["nodes"])
+        dt, red, shape = item["dtype"], item["reduce"], item["shape"]
+        kind = KIND[red]
+        t = fx_tune_time(tape, pool.views(dt, shape[0] * shape[1], item["n_inputs"]), pool.out,
+                         shape, kind, [cfgs[i][0] for i in cells], ws=pool.ws if kind else None,
+                         warmup=warmup, reps=reps, dt=DTYPE[dt])
+        med = [statistics.median(v) for v in t]
+        best_pairs.append((rec["best_ms"], med[0]))
+        still_best.append(med[0] <= 1.05 * min(x for x in rec["ms"][:-1]
+                                               if x is not None and x == x))
+        sample_pairs += [(rec["ms"][i], m) for i, m in zip(cells[1:], med[1:])]
+        if progress and k % progress == 0:
+            print("noise %d/%d  %.0fs" % (k, len(recs), time.time() - t0), flush=True)
+    return {"records": len(recs), "sample_fraction": frac,
+            "argmin": noise_summary(best_pairs),
+            "argmin_within_1.05_of_stored_best": round(sum(still_best) / max(1, len(still_best)), 4),
+            "random_cells": noise_summary(sample_pairs)}
+
+
 def record_grid(r):
     """The (config, labels) grid a database record's times refer to."""
     return grid(r["reduce"], r["dtype"], r.get("cus", 256))
@@ -207,7 +264,18 @@ def main(argv=None):
     ap.add_argument("--retime-default", default=None, metavar="IN_DB",
                     help="re-measure the library-default time of every record of IN_DB "
                          "into --db")
+    ap.add_argument("--noise", nargs="+", default=None, metavar="IN_DB",
+                    help="re-time every record's argmin and a random --frac of its cells; "
+                         "write the noise report to --db")
+    ap.add_argument("--frac", type=float, default=0.01)
     a = ap.parse_args(argv)
+    if a.noise:
+        lib()
+        recs = [r for p in a.noise for r in load_db(p).values()]
+        rep = retime_noise(recs, Pool(a.max_n), frac=a.frac, progress=200)
+        json.dump(rep, open(a.db, "w"), indent=1)
+        print(json.dumps(rep, indent=1), flush=True)
+        return 0
     if a.retime_default:
         lib()
         recs = list(load_db(a.retime_default).values())

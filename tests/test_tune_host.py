@@ -38,3 +38,22 @@ def test_tuning_items():
     assert {it["dtype"] for it in items} == {"f32", "bf16"}
     assert trees.tuning_item(5, 7) == trees.tuning_item(5, 7)
     assert trees.tuning_item(6, 7) != trees.tuning_item(5, 7)
+
+
+def test_noise_summary_recovers_a_known_spread():
+    # two independent measurements per cell, each with 3% lognormal noise:
+    # the estimate from their relative differences returns about 3%
+    import numpy as np
+    from paper_2604_22242_amd.tune import noise_summary
+    rng = np.random.default_rng(1)
+    true = rng.uniform(0.01, 1.0, 20000)
+    a = true * np.exp(rng.normal(0, 0.03, true.size))
+    b = true * np.exp(rng.normal(0, 0.03, true.size))
+    rep = noise_summary(list(zip(a, b)))
+    assert rep["cells"] == true.size
+    assert abs(rep["cv_estimate"] - 0.03) < 0.002, rep
+    assert abs(rep["median_ratio"] - 1.0) < 0.002
+    # identical re-times: no spread; unusable cells are skipped
+    rep = noise_summary([(1.0, 1.0), (2.0, 2.0), (float("nan"), 1.0), (0.0, 1.0)])
+    assert rep["cells"] == 2 and rep["cv_estimate"] == 0.0 and rep["within_2pct"] == 1.0
+    assert noise_summary([])["cells"] == 0
