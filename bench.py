@@ -431,6 +431,10 @@ def main():
                     help="fused FP32 steps, then the same steps with BF16 storage, plus one "
                          "1 GiB copy (the known-size kernel that scales hardware byte "
                          "counters); no CPU baseline")
+    ap.add_argument("--profile-set", choices=("step", "views", "paper", "batch"), default="step",
+                    help="with --profile: which kernels to run (the matrix-workload step, the "
+                         "paper's strided-view expressions, the paper's expression suite, or the "
+                         "4096-expression batch), always followed by the 1 GiB copy")
     a = ap.parse_args()
     if a.profile:
         a.no_extra = a.no_cpu = True
@@ -444,6 +448,16 @@ def main():
     import paper_2604_22242_amd as fx
     fx.lib()
     stream = torch.cuda.current_stream()
+    if a.profile and a.profile_set != "step":
+        run = {"views": paper_views_detail, "paper": paper_suite_detail,
+               "batch": batch_detail}[a.profile_set]
+        log("bench: profile set %s, %d repetitions" % (a.profile_set, a.steps))
+        res = run(fx, torch, stream, a.steps)
+        torch.cuda.empty_cache()
+        log("bench: 1 GiB reference copy")
+        copy_ceiling(fx, torch, stream, nbytes=1 << 30, reps=1)
+        print(json.dumps({"profile_set": a.profile_set, "detail": res}), flush=True)
+        return
     log("bench: fused FP32 %dx%d, %d warm-up + %d timed steps" % (ROWS, COLS, a.warmup, a.steps))
     wl = Workload(fx, torch, "f32", ROWS, COLS)
     wall, ms = time_steps(torch, wl.fused, a.steps, a.warmup, stream)

@@ -350,10 +350,26 @@ __device__ __forceinline__ void stage(const Binary<Op, A, B>& e, const tile_ctx<
   stage<TOFF + trans_count<A>::value, N>(e.b, x, rows, cols);
 }
 
-// Z (dense rows x cols) = E over a grid of tiles.
-// (blockIdx.x: tile row, blockIdx.y: tile column; launching the partner
-// tiles (I, J) and (J, I) side by side, to find a transposed operand's tile in
-// the last-level cache, measured slower on the 10k x 10k expressions.)
+// Workgroups are dispatched to the eight XCDs round-robin by block id, and
+// each XCD has its own L2.  Where a leading dimension is not a multiple of
+// the 128-byte line (10000 floats = 40000 B), vertically adjacent tiles
+// share the line their column runs straddle; under the plain order those two
+// tiles run on different XCDs and both fetch it from HBM (12% more reads for
+// submatrices, 25% with transposes).  xcd_order() gives each XCD a
+// contiguous run of tiles instead (a bijection on [0, G)), so the second
+// fetch of a shared line is an L2 hit.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t G) {
+  const uint32_t per = G / kXcds, extra = G % kXcds;
+  const uint32_t xcd = b % kXcds, k = b / kXcds;
+  return xcd * per + (xcd < extra ? xcd : extra) + k;
+}
+
+// Z (dense rows x cols) = E over a grid of tiles, numbered down the tile
+// columns (tile t: tile row t % tile_rows, tile column t / tile_rows) and
+// taken in xcd_order.  (Launching the partner tiles (I, J) and (J, I) side
+// by side, to find a transposed operand's tile in the last-level cache,
+// measured slower on the 10k x 10k expressions.)
 // Tile geometry: with transposed leaves the tile is (16 N) x 64 (square for
 // FP32, the LDS staging tile); without them it is (64 N) x 16, so that each
 // column of every leaf is read in 1 KB-or-longer contiguous runs (square
@@ -363,12 +379,13 @@ template <int KT> constexpr int kColsPerTile = KT > 0 ? kTileCols : 16;
 
 template <class E, class T, int N>
 __global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, int64_t rows,
-                                                      int64_t cols) {
+                                                      int64_t cols, uint32_t tile_rows) {
   using C = typename E::ct;
   constexpr int KT = trans_count<E>::value;
   constexpr int RV = kRowVecs<KT>, CG = kTileThreads / RV, TC = kColsPerTile<KT>;
   __shared__ C lds[KT > 0 ? KT * kTileBuf<N> : 1];
-  const tile_ctx<C, N> x{lds, (int64_t)blockIdx.x * RV * N, (int64_t)blockIdx.y * TC};
+  const uint32_t t = xcd_order(blockIdx.x, gridDim.x);
+  const tile_ctx<C, N> x{lds, (int64_t)(t % tile_rows) * RV * N, (int64_t)(t / tile_rows) * TC};
   if constexpr (KT > 0) {
     static_assert(RV * N == kTileRows<N> && TC == kTileCols, "staging tile geometry");
     stage<0, N>(e, x, rows, cols);
@@ -485,7 +502,7 @@ template <class E>
 __global__ __launch_bounds__(kTileThreads) void k_ew2d_pair(E e, pair_tab tab, float* __restrict__ z,
                                                            int64_t n) {
   __shared__ float lds[2 * kPairMats * kPairBuf];
-  const int64_t p = blockIdx.x;
+  const int64_t p = xcd_order(blockIdx.x, gridDim.x);
   int64_t J = (int64_t)((::sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
   while (J * (J + 1) / 2 > p) --J;
   while ((J + 1) * (J + 2) / 2 <= p) ++J;
@@ -630,13 +647,15 @@ int eval_views(T* z, const E& e, hipStream_t st) {
     }
   }
   const int64_t tc = ceil_div(cols, kColsPerTile<KT>);
-  if (tc > 65535) return fail(FX_E_UNSUPPORTED, "%lld columns exceed the tile grid", (long long)cols);
+  const int64_t tr = ceil_div(rows, (int64_t)kRowVecs<KT> * (vec ? NV : 1));
+  if (tr * tc > 0x7fffffff)
+    return fail(FX_E_UNSUPPORTED, "%lld x %lld exceeds the tile grid", (long long)rows, (long long)cols);
   if (vec) {
-    const dim3 grid((unsigned)ceil_div(rows, (int64_t)kRowVecs<KT> * NV), (unsigned)tc);
-    hipLaunchKernelGGL((k_ew2d<E, T, NV>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
+    hipLaunchKernelGGL((k_ew2d<E, T, NV>), dim3((unsigned)(tr * tc)), dim3(kTileThreads), 0, st, e,
+                       z, rows, cols, (uint32_t)tr);
   } else {
-    const dim3 grid((unsigned)ceil_div(rows, (int64_t)kRowVecs<KT>), (unsigned)tc);
-    hipLaunchKernelGGL((k_ew2d<E, T, 1>), grid, dim3(kTileThreads), 0, st, e, z, rows, cols);
+    hipLaunchKernelGGL((k_ew2d<E, T, 1>), dim3((unsigned)(tr * tc)), dim3(kTileThreads), 0, st, e,
+                       z, rows, cols, (uint32_t)tr);
   }
   return hip_check(hipGetLastError(), "k_ew2d launch");
 }
