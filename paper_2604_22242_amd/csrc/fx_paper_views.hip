@@ -92,7 +92,14 @@ int fx_paper_view_expr(int which, fx_dtype dt, const void* const* in, const doub
           v.n_rows = o.n_rows;  // the common length
           return v;
         };
-        return eval(z, (d(X, -1) + d(X, 1)) % (d(Y, -1) + d(Y, 1)), nullptr, S(stream));
+        // diagonal elements are one per column: every load is its own
+        // scattered access, so vectors buy nothing and the few thousand
+        // elements are spread thin (64-thread blocks, one element each)
+        // to have as many loads in flight over as many CUs as possible
+        const fx_launch thin{64, 1, (int32_t)sizeof(T),
+                             (int32_t)std::max<int64_t>(1, std::min<int64_t>(ceil_div(o.n_rows, 64),
+                                                                            1 << 20))};
+        return eval(z, (d(X, -1) + d(X, 1)) % (d(Y, -1) + d(Y, 1)), &thin, S(stream));
       }
     }
     return fail(FX_E_ARG, "unknown view expression %d", which);
