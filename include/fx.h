@@ -346,8 +346,15 @@ int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* 
  * all of storage dtype dt and shape `shape`).  kind 0: element-wise, `out`
  * has the storage dtype; FX_R_ACCU / FX_R_NORM: one double; FX_R_COLSUM /
  * FX_R_ROWSUM: accumulator dtype vector.  ws as for the fused reductions
- * (fx_workspace_bytes of the same kind).  A zero EPT in cfg means 2 for element-wise
- * tapes (the interpreter runs both vectors in one pass). */
+ * (fx_workspace_bytes of the same kind, which covers both the library's and
+ * the interpreter's defaults).  Fields of cfg left at 0 take the
+ * interpreter's own defaults, chosen on the autotuner's training trees:
+ * element-wise 64 threads, EPT 1, 16-byte vectors, one tile per block;
+ * accu / norm 512 threads, EPT 2 (1 for half types), 2 blocks per CU;
+ * column sums 256 threads, EPT 2 (1 for half types), one block per column
+ * when there are at least as many columns as CUs; row sums 256 threads,
+ * EPT 2, one row per thread, 64 column chunks.  The split default applies
+ * only when all of cfg is 0 (or cfg is NULL). */
 int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);

@@ -287,6 +287,12 @@ __device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF, SLOTS>& e, in
 
 template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static constexpr int value = 2; };
 
+// The launch configuration of an interpreted tape: the fields of cfg (NULL:
+// all) left at 0 take the interpreter's defaults for the kind and storage
+// width; split may stay 0 (the library's heuristic).  Defined with the other
+// launch heuristics in fx_host.hip.
+fx_launch tape_launch(int kind, int elem, int64_t n_cols, const fx_launch* cfg);
+
 // Evaluate a tape of storage type T (defined once per dtype, in its own
 // translation unit, to keep compile times short).
 template <class T>
@@ -302,18 +308,14 @@ int tape_eval_impl(const tape_prog& prog, const void* const* inputs, fx_shape s,
   e.n_rows = s.n_rows;
   e.n_cols = s.n_cols;
   e.prog = prog;
+  // fields left at 0 take the interpreter's own defaults, not the library's
+  const fx_launch c = tape_launch(kind, (int)sizeof(T), s.n_cols, cfg);
   switch (kind) {
-    case 0: {
-      // two vectors per thread by default: the interpreter runs them as one
-      // pass of kPassLanes lanes, halving fetches and dispatches per element
-      fx_launch c = cfg ? *cfg : fx_launch{0, 0, 0, 0};
-      if (c.ept == 0) c.ept = 2;
-      return eval(static_cast<T*>(out), e, &c, st);
-    }
-    case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, cfg, st);
-    case FX_R_NORM: return reduce_full<map_sq>(e, out, ws, ws_bytes, cfg, st);
+    case 0: return eval(static_cast<T*>(out), e, &c, st);
+    case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, &c, st);
+    case FX_R_NORM: return reduce_full<map_sq>(e, out, ws, ws_bytes, &c, st);
     case FX_R_COLSUM: case FX_R_ROWSUM:
-      return reduce_dim(kind, e, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, st);
+      return reduce_dim(kind, e, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, &c, st);
   }
   return fail(FX_E_ARG, "unknown kind %d for a tape", kind);
 }
