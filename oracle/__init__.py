@@ -420,7 +420,10 @@ def check(result, value, mu, dtype: str, out_dtype: str | None = None):
         # values at or beyond the FP16 overflow threshold round to +-inf
         ovf = ~inf & (np.abs(v) >= F16_OVERFLOW)
         ok = np.where(ovf, r == np.copysign(np.inf, v), ok)
-    rel_branch = np.asarray(TOL[dtype] * np.abs(v) >= 4.0 * compute_unit(dtype) * np.asarray(mu))
+    # results that pass only through the running-bound branch: beyond the
+    # pure relative bound (the tolerance, or for a half-format output its
+    # final rounding, u_half |v|), yet within the allowed error
+    rel_tol = U_HALF[out_dtype] if out_dtype in U_HALF else TOL[dtype]
     with np.errstate(invalid="ignore", divide="ignore"):
         rel = np.where(v != 0, err / np.abs(v), err)
         # infinities that match (FP16 overflow) are reported as exact
@@ -434,7 +437,7 @@ def check(result, value, mu, dtype: str, out_dtype: str | None = None):
         "fail": int(r.size - np.count_nonzero(ok)),
         "max_rel": float(np.nanmax(rel)) if r.size else 0.0,
         "max_err_over_allowed": float(np.nanmax(over)) if r.size else 0.0,
-        "cancellation_dominated": int(np.count_nonzero(~rel_branch)),
+        "needed_mu_branch": int(np.count_nonzero(ok & ~np.isinf(r) & (err > rel_tol * np.abs(v)))),
     }
     return ok, report
 

@@ -17,8 +17,8 @@ ROWS = COLS = 8192
 
 
 def _report(name, rep):
-    print("%-34s n=%-9d max_rel=%.3e err/allowed=%.3f cancellation=%d" % (
-        name, rep["n"], rep["max_rel"], rep["max_err_over_allowed"], rep["cancellation_dominated"]),
+    print("%-34s n=%-9d max_rel=%.3e err/allowed=%.3f needed_mu_branch=%d" % (
+        name, rep["n"], rep["max_rel"], rep["max_err_over_allowed"], rep["needed_mu_branch"]),
         flush=True)
 
 

@@ -420,3 +420,18 @@ def test_paper_view_expressions():
     assert shape == (m - 1, 1) and np.array_equal(v, d(mats[0]) * d(mats[1]))
     v, _ = oracle.evaluate(e, [ins[0], ins[0]], "f64", shape=shape)     # X = Y: a square
     assert np.all(v >= 0)
+
+
+def test_check_reports_results_that_need_the_running_bound():
+    # three results of value 1 with a running bound of 100 units: exact, off by
+    # 1e-5 (beyond the 1e-6 relative tolerance, inside 4*u*mu = 2.4e-5) and off
+    # by 1e-4 (a failure); only the middle one passes through the mu branch
+    v = np.ones(3)
+    mu = np.full(3, 100.0)
+    ok, rep = oracle.check(np.array([1.0, 1.0 + 1e-5, 1.0 + 1e-4]), v, mu, "f32")
+    assert ok.tolist() == [True, True, False]
+    assert rep["fail"] == 1 and rep["needed_mu_branch"] == 1
+    # a half-format output: its own rounding (u_half |v|) is the relative part
+    ok, rep = oracle.check(np.array([1.0 + 2.0 ** -9, 1.0 + 2.0 ** -7]), np.ones(2), np.full(2, 1e5),
+                           "f32", out_dtype="bf16")
+    assert ok.all() and rep["needed_mu_branch"] == 1
