@@ -72,6 +72,8 @@ int check_launch(const fx_launch* c) {
 //     tile's loads are issued together), with enough column chunks for 8
 //     waves per CU.
 static constexpr int kReduceBlocksPerCU = 2;
+static constexpr int kReduceMinBlocks = 32;
+static constexpr int kReduceMinTilesPerBlock = 4;
 static constexpr int kColsumBlocksPerCU = 8;
 static constexpr int kRowsumWavesPerCU = 8;
 constexpr int kRowsumMinCols = 32;
@@ -95,9 +97,16 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
     const int64_t tiles = std::max<int64_t>(1, ceil_div(n, (int64_t)L.block * L.ept * vec16));
     // full reductions: one ticket per block; below 2^24 elements the tickets
     // of two blocks per CU cost more than the extra bandwidth buys (measured:
-    // 8.0 vs 10.3 us at 2^20), above it two per CU keep HBM busier
+    // 8.0 vs 10.3 us at 2^20), above it two per CU keep HBM busier.  Small
+    // ones also give every block at least four tiles (but keep 32 blocks):
+    // the single-pass finish is a few serial round trips plus one ticket per
+    // block, which the work of a one- or two-tile block does not cover
+    // (2^20 elements: 128 blocks 6.3 us, 256 blocks 7.3 us).
     const int64_t per_cu = n < ((int64_t)1 << 24) ? 1 : kReduceBlocksPerCU;
-    const int64_t want = ew ? tiles : std::min<int64_t>(tiles, cus * per_cu);
+    const int64_t want =
+        ew ? tiles
+           : std::min<int64_t>(std::min<int64_t>(tiles, cus * per_cu),
+                               std::max<int64_t>(kReduceMinBlocks, tiles / kReduceMinTilesPerBlock));
     L.split = c.split ? c.split : (int)std::min<int64_t>(want, 1 << 30);
   } else if (kind == FX_R_COLSUM) {
     L.block = c.block ? c.block : elem >= 4 ? 512 : 256;
