@@ -120,3 +120,60 @@ def test_precision_workload_2_28(dtype, dist):
         exact = float(np.dot(raw[0], raw[1]))
         print("accu(X%%Y) %s vs pre-storage draws: rel %.3e" % (
             dtype, abs(s.item() - exact) / abs(exact)), flush=True)
+
+
+def test_beyond_2_31_elements():
+    """The largest size class: n = 2^31 + 37 FP32 elements (8.6 GB per
+    array), past every 32-bit index.  Z = X % Y + 2 W and accu(X % W) with
+    X = Y = 1 through the compiled kernels, a tape and a run-time generated
+    kernel: Z on windows at the start, the middle and the end (across element
+    2^31) against the oracle, the sums against the oracle over all n elements, and accu(X % Y)
+    = n exactly."""
+    torch, fx = need_gpu()
+    n = (1 << 31) + 37
+    print("n = %d" % n, flush=True)
+    w = synth.fill(7, 2, n, "f32")
+    W = torch.from_numpy(w).cuda()
+    ones = torch.ones(n, dtype=torch.float32, device="cuda")
+    Z = torch.empty(n, dtype=torch.float32, device="cuda")
+    ws = fx.workspace(fx.R_ACCU, fx.F32, (n, 1))
+    s_ones = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.fx_accu_xy(ones, ones, s_ones, ws)
+    s_w = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.fx_accu_xy(ones, W, s_w, ws)
+    torch.cuda.synchronize()
+    assert s_ones.item() == n
+    # the first elements, the middle, and the last 4096 (which cross element 2^31)
+    wins = [(0, 4096), ((1 << 30) - 2048, (1 << 30) + 2048), (n - 4096, n)]
+    assert wins[-1][0] < (1 << 31) < wins[-1][1]
+
+    def check_windows(what):
+        torch.cuda.synchronize()
+        for a, b in wins:
+            one = np.ones(b - a, np.float32)
+            v, mu = oracle.evaluate(oracle.EXPRS["c1_z"], [one, one, w[a:b]], "f32")
+            assert_close(Z[a:b].cpu().numpy().astype(np.float64), v, mu, "f32",
+                         "%s Z[%d:%d]" % (what, a, b))
+        Z.fill_(float("nan"))
+
+    fx.fx_c1_z(ones, ones, W, Z)
+    check_windows("compiled")
+    nodes = [("leaf", -1, -1, 0, 0.0), ("leaf", -1, -1, 1, 0.0), ("mul", 0, 1, -1, 0.0),
+             ("leaf", -1, -1, 2, 0.0), ("const", -1, -1, -1, 2.0), ("mul", 4, 3, -1, 0.0),
+             ("add", 2, 5, -1, 0.0)]
+    fx.fx_tape_eval(fx.Tape(nodes), [ones, ones, W], Z, (n, 1))
+    check_windows("tape")
+    fx.Rtc(nodes, fx.F32).eval([ones, ones, W], Z, (n, 1))
+    check_windows("run-time source")
+    xw = [("leaf", -1, -1, 0, 0.0), ("leaf", -1, -1, 1, 0.0), ("mul", 0, 1, -1, 0.0)]
+    s_tape = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.fx_tape_eval(fx.Tape(xw), [ones, W], s_tape, (n, 1), fx.R_ACCU, ws)
+    s_rtc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fx.Rtc(xw, fx.F32, fx.R_ACCU).eval([ones, W], s_rtc, (n, 1), ws)
+    torch.cuda.synchronize()
+    del Z, W, ones
+    torch.cuda.empty_cache()
+    v, mu = oracle.evaluate(oracle.EXPRS["xy"], [np.ones(n, np.float32), w], "f32", reduce="accu")
+    for what, s in (("compiled", s_w), ("tape", s_tape), ("run-time source", s_rtc)):
+        _report("accu(1 %% W) n=2^31+37 %s" % what,
+                assert_close(s.cpu().numpy(), v, mu, "f32", "%s accu beyond 2^31" % what))
