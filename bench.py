@@ -57,7 +57,7 @@ class Workload:
         n = rows * cols
         self.X, self.Y, self.W = make_inputs(dtype, n)
         tdt = self.X.dtype
-        acc = torch.float32
+        acc = torch.float64 if dtype == "f64" else torch.float32  # column sums' dtype
         self.Z = torch.empty(n, dtype=tdt, device="cuda")
         self.cs = torch.empty(cols, dtype=acc, device="cuda")
         self.nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -66,7 +66,8 @@ class Workload:
         self.ws_n = fx.workspace(fx.R_NORM, dt, self.shape)
         esz = self.X.element_size()
         # algorithmic bytes: distinct inputs read once, outputs written once
-        self.bytes = {"z": 4 * n * esz, "colsum": 3 * n * esz + cols * 4, "norm": 2 * n * esz + 8}
+        self.bytes = {"z": 4 * n * esz, "colsum": 3 * n * esz + cols * self.cs.element_size(),
+                      "norm": 2 * n * esz + 8}
         self.tmp = None
 
     def fused(self, which, stream):
@@ -487,6 +488,16 @@ def main():
         detail["bf16_speedup_vs_unfused"] = {r: round(bums[r] / bms[r], 3) for r in RESULTS}
         detail["bf16_speedup_vs_fp32_storage"] = {r: round(ms[r] / bms[r], 3) for r in RESULTS}
         del wb
+        torch.cuda.empty_cache()
+        log("bench: fused FP64 storage")
+        wd = Workload(fx, torch, "f64", ROWS, COLS)
+        _, dms = time_steps(torch, wd.fused, a.steps, a.warmup, stream)
+        _, dums = time_steps(torch, wd.unfused, a.steps, a.warmup, stream)
+        detail["fp64_fused"] = {r: {"ms": round(dms[r], 5),
+                                    "GB/s": round(wd.bytes[r] / (dms[r] * 1e-3) / 1e9, 1)}
+                                for r in RESULTS}
+        detail["fp64_speedup_vs_unfused"] = {r: round(dums[r] / dms[r], 3) for r in RESULTS}
+        del wd
         torch.cuda.empty_cache()
         log("bench: copy ceiling")
         detail["copy_ceiling_GB/s"] = round(copy_ceiling(fx, torch, stream), 1)
