@@ -153,18 +153,22 @@ def event_ms(torch, stream, fn, reps):
 
 def c1_detail(fx, torch, stream, reps):
     """The small vector workload, n = 2^20 FP32 (16 MiB: it fits the 256 MB
-    last-level cache): Z = X%Y + 2W and accu(X%Y), warm (back-to-back
-    launches) and cold (a 512 MiB write between launches, outside the
-    timed events)."""
+    last-level cache): Z = X%Y + 2W and accu(X%Y), and its u32 form
+    Z = (X^Y) + 3W, warm (back-to-back launches) and cold (a 512 MiB write
+    between launches, outside the timed events)."""
     import synth
     n = 1 << 20
     X, Y, W = [torch.from_numpy(synth.fill(1, t, n, "f32")).cuda() for t in range(3)]
+    U = [torch.from_numpy(synth.fill(1, t, n, "u32", "uint31").view("int32")).cuda()
+         for t in range(3)]
     Z = torch.empty(n, device="cuda")
+    ZU = torch.empty(n, dtype=torch.int32, device="cuda")
     s = torch.zeros(1, dtype=torch.float64, device="cuda")
     ws = fx.workspace(fx.R_ACCU, fx.F32, (n, 1))
     flush = torch.empty(128 << 20, device="cuda")
     runs = {"z": (lambda: fx.fx_c1_z(X, Y, W, Z, stream=stream), 16 * n),
-            "accu": (lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), 8 * n)}
+            "accu": (lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), 8 * n),
+            "u32_z": (lambda: fx.fx_c1_z(*U, ZU, stream=stream), 16 * n)}
     out = {}
     with torch.cuda.stream(stream):
         for name, (fn, nbytes) in runs.items():
@@ -429,9 +433,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the fused FP32 steps")
     ap.add_argument("--profile", action="store_true",
-                    help="fused FP32 steps, then the same steps with BF16 storage, plus one "
-                         "1 GiB copy (the known-size kernel that scales hardware byte "
-                         "counters); no CPU baseline")
+                    help="fused FP32 steps, then the same steps with BF16 and FP64 storage, "
+                         "plus one 1 GiB copy (the known-size kernel that scales hardware "
+                         "byte counters); no CPU baseline")
     ap.add_argument("--profile-set", choices=("step", "views", "paper", "batch"), default="step",
                     help="with --profile: which kernels to run (the matrix-workload step, the "
                          "paper's strided-view expressions, the paper's expression suite, or the "
@@ -522,11 +526,12 @@ def main():
     if a.profile:
         del wl
         torch.cuda.empty_cache()
-        log("bench: fused BF16 storage steps")
-        wb = Workload(fx, torch, "bf16", ROWS, COLS)
-        time_steps(torch, wb.fused, a.steps, a.warmup, stream)
-        del wb
-        torch.cuda.empty_cache()
+        for dt in ("bf16", "f64"):
+            log("bench: fused %s storage steps" % dt.upper())
+            wb = Workload(fx, torch, dt, ROWS, COLS)
+            time_steps(torch, wb.fused, a.steps, a.warmup, stream)
+            del wb
+            torch.cuda.empty_cache()
         log("bench: 1 GiB reference copy")
         copy_ceiling(fx, torch, stream, nbytes=1 << 30, reps=1)
 
