@@ -349,7 +349,8 @@ int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* 
  * (fx_workspace_bytes of the same kind, which covers both the library's and
  * the interpreter's defaults).  Fields of cfg left at 0 take the
  * interpreter's own defaults, chosen on the autotuner's training trees:
- * element-wise 64 threads, EPT 1, 16-byte vectors, one tile per block;
+ * element-wise 64 threads, EPT 1, 16-byte vectors, one tile per block (256
+ * threads, EPT 2 for 4- and 8-byte types from 2^20 elements on);
  * accu / norm 512 threads, EPT 2 (1 for half types), 2 blocks per CU;
  * column sums 256 threads, EPT 2 (1 for half types), one block per column
  * when there are at least as many columns as CUs; row sums 256 threads,

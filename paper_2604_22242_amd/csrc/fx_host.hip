@@ -142,12 +142,13 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
 // best geometric-mean time (over each item's best) on the autotuner's
 // 20,000 random training trees, per kind and storage width; on the 2,000
 // held-out trees these give 1.10x the best against 1.47x for the library
-// defaults.  Column sums keep the split heuristic when there are fewer
+// defaults.  Element-wise FP32 / FP64 tapes of 2^20 elements or more take
+// two vectors per thread.  Column sums keep the split heuristic when there are fewer
 // columns than CUs (one block per column would leave the chip idle); row
 // sums use one row per thread in 64 column chunks.  The split default
 // applies only when the whole configuration is left at 0: a caller that
 // sets any field and leaves split at 0 gets the library's split heuristic.
-fx_launch tape_launch(int kind, int elem, int64_t n_cols, const fx_launch* cfg) {
+fx_launch tape_launch(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_launch* cfg) {
   fx_launch c = cfg ? *cfg : fx_launch{0, 0, 0, 0};
   const bool all_default = !c.block && !c.ept && !c.vec_bytes && !c.split;
   const bool half = elem == 2;
@@ -157,7 +158,14 @@ fx_launch tape_launch(int kind, int elem, int64_t n_cols, const fx_launch* cfg) 
     case FX_R_ACCU: case FX_R_NORM: d = fx_launch{512, half ? 1 : 2, 16, 2 * cus}; break;
     case FX_R_COLSUM: d = fx_launch{256, half ? 1 : 2, 16, n_cols >= cus ? 1 : 0}; break;
     case FX_R_ROWSUM: d = fx_launch{256, 2, elem, 64}; break;
-    default: d = fx_launch{64, 1, 16, 0}; break;
+    default:
+      // two vectors per thread fill an interpreter pass for 4- and 8-byte
+      // types; they pay off once there are enough elements to keep the chip
+      // busy with fewer threads (training trees: 1.073x the best against
+      // 1.096x for one vector everywhere)
+      d = elem >= 4 && n_rows * n_cols >= ((int64_t)1 << 20) ? fx_launch{256, 2, 16, 0}
+                                                            : fx_launch{64, 1, 16, 0};
+      break;
   }
   if (!c.block) c.block = d.block;
   if (!c.ept) c.ept = d.ept;
@@ -222,7 +230,7 @@ size_t fx_workspace_bytes(int kind, fx_dtype dt, fx_shape shape, const fx_launch
   // the same call may evaluate a run-time tape, whose defaults differ:
   // enough for both
   if (kind != FX_R_DOT) {
-    const fx_launch t = tape_launch(kind, elem, shape.n_cols, cfg);
+    const fx_launch t = tape_launch(kind, elem, shape.n_rows, shape.n_cols, cfg);
     launch T = resolve(kind, elem, shape.n_rows, shape.n_cols, &t, true);
     b = std::max(b, workspace_for(kind, shape.n_rows, shape.n_cols, T, 16 / elem).total());
   }

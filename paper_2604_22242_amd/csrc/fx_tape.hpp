@@ -291,7 +291,7 @@ template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static con
 // all) left at 0 take the interpreter's defaults for the kind and storage
 // width; split may stay 0 (the library's heuristic).  Defined with the other
 // launch heuristics in fx_host.hip.
-fx_launch tape_launch(int kind, int elem, int64_t n_cols, const fx_launch* cfg);
+fx_launch tape_launch(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_launch* cfg);
 
 // Evaluate a tape of storage type T (defined once per dtype, in its own
 // translation unit, to keep compile times short).
@@ -309,7 +309,7 @@ int tape_eval_impl(const tape_prog& prog, const void* const* inputs, fx_shape s,
   e.n_cols = s.n_cols;
   e.prog = prog;
   // fields left at 0 take the interpreter's own defaults, not the library's
-  const fx_launch c = tape_launch(kind, (int)sizeof(T), s.n_cols, cfg);
+  const fx_launch c = tape_launch(kind, (int)sizeof(T), s.n_rows, s.n_cols, cfg);
   switch (kind) {
     case 0: return eval(static_cast<T*>(out), e, &c, st);
     case FX_R_ACCU: return reduce_full<map_id>(e, out, ws, ws_bytes, &c, st);
