@@ -190,7 +190,9 @@ def c1_detail(fx, torch, stream, reps):
 
 def precision_detail(fx, torch, stream, reps):
     """The C1 expressions at 2^28 elements: BF16 and FP16 storage against the
-    FP32 storage reference (Z = X%Y + 2W and accu(X%Y))."""
+    FP32 storage reference (Z = X%Y + 2W and accu(X%Y)), plus norm_fro(X-Y)
+    and sum(X%Y, 0) with the vector read as a 2^14 x 2^14 column-major
+    matrix."""
     import synth
     m = 1 << 28
     out = {}
@@ -203,15 +205,25 @@ def precision_detail(fx, torch, stream, reps):
         s = torch.zeros(1, dtype=torch.float64, device="cuda")
         ws = fx.workspace(fx.R_ACCU, fx.dtype_code(X), (m, 1))
         es = X.element_size()
+        side = 1 << 14
+        sq = (side, side)
+        wn = fx.workspace(fx.R_NORM, fx.dtype_code(X), sq)
+        wc = fx.workspace(fx.R_COLSUM, fx.dtype_code(X), sq)
+        cs = torch.empty(side, dtype=torch.float32, device="cuda")
         zt = event_ms(torch, stream, lambda: fx.fx_c1_z(X, Y, W, Z, stream=stream), reps)
         at = event_ms(torch, stream, lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), reps)
+        nt = event_ms(torch, stream, lambda: fx.fx_norm_fro_diff(X, Y, s, sq, wn, stream=stream), reps)
+        ct = event_ms(torch, stream, lambda: fx.fx_colsum_xy(X, Y, cs, sq, wc, stream=stream), reps)
         out[dt] = {"z_ms": round(zt, 4), "z_GB/s": round(4 * es * m / zt / 1e6, 1),
-                   "accu_ms": round(at, 4), "accu_GB/s": round(2 * es * m / at / 1e6, 1)}
+                   "accu_ms": round(at, 4), "accu_GB/s": round(2 * es * m / at / 1e6, 1),
+                   "norm_ms": round(nt, 4), "norm_GB/s": round(2 * es * m / nt / 1e6, 1),
+                   "colsum_ms": round(ct, 4),
+                   "colsum_GB/s": round((2 * es * m + 4 * side) / ct / 1e6, 1)}
         del X, Y, W, Z
         torch.cuda.empty_cache()
     for dt in ("bf16", "f16"):
-        out[dt]["z_speedup_vs_f32_storage"] = round(out["f32"]["z_ms"] / out[dt]["z_ms"], 3)
-        out[dt]["accu_speedup_vs_f32_storage"] = round(out["f32"]["accu_ms"] / out[dt]["accu_ms"], 3)
+        for r in ("z", "accu", "norm", "colsum"):
+            out[dt][r + "_speedup_vs_f32_storage"] = round(out["f32"][r + "_ms"] / out[dt][r + "_ms"], 3)
     return out
 
 
