@@ -128,7 +128,9 @@ int fx_synchronize(void* stream);
 
 /* Workspace bytes needed by reduction `kind` (FX_R_*) over an expression of
  * storage dtype `dt` and shape `shape` under launch configuration `cfg`
- * (NULL = defaults).  Returns 0 on bad arguments. */
+ * (NULL = defaults).  The size covers both the fused calls and a run-time
+ * tape of the same kind (whose unset fields take the interpreter's
+ * defaults).  Returns 0 on bad arguments. */
 size_t fx_workspace_bytes(int kind, fx_dtype dt, fx_shape shape, const fx_launch* cfg);
 
 /* The configuration the library would use for reduction kind `kind`
