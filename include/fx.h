@@ -471,6 +471,28 @@ int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
                  const fx_launch* cfgs, int32_t n_cfgs, int32_t warmup, int32_t reps,
                  float* ms, void* stream);
 
+/* The exhaustive autotuner's configuration grid for a tape of result kind
+ * `kind` (0 or FX_R_*) and storage dtype dt: block {64, 128, 256, 512} x EPT
+ * {1, 2} x vector {one element, 16 bytes} x four split values of the kind
+ * (element-wise 0, 2, 8, 32 blocks per CU; accu / norm 1, 2, 4, 8 blocks per
+ * CU; column sums 0, 1, 4, 16 chunks per column; row sums 0, 16, 64, 256
+ * column chunks; 0 = the library's choice), then the default (all 0).
+ * Writes the 65 configurations to out[0..cap) and returns their count; with
+ * out NULL or cap too small, only the count.  Negative fx_status on a bad
+ * kind or dtype. */
+int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t cap);
+
+/* Exhaustive autotuning: time tape t (arguments as for fx_tape_eval) under
+ * every configuration of fx_tune_grid, each `warmup` untimed launches and
+ * then the median of `reps` timed ones, and return the fastest in *best
+ * and its median time in *best_ms.  The default configuration is timed but
+ * never chosen.  Configurations whose workspace exceeds ws_bytes, or that
+ * are not compiled, are skipped; FX_E_UNSUPPORTED if none runs.
+ * Synchronous. */
+int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes, int32_t warmup,
+                int32_t reps, fx_launch* best, float* best_ms, void* stream);
+
 /* The learned cost model: a two-layer perceptron (standardised features ->
  * hidden ReLU layer -> one softmax head per launch knob), trained on the
  * autotuner's best configurations with softmax cross-entropy and Adam, by

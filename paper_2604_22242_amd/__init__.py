@@ -132,6 +132,9 @@ _SIGS = {
     "fx_tune_time": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                           ctypes.POINTER(ctypes.c_float), _P]),
+    "fx_tune_grid": (ctypes.c_int32, [_I, _I, _LP, ctypes.c_int32]),
+    "fx_autotune": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
+                         ctypes.c_int32, ctypes.c_int32, _LP, ctypes.POINTER(ctypes.c_float), _P]),
     "fx_model_create": (_I, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                              ctypes.c_int32, ctypes.POINTER(_P)]),
     "fx_model_num_params": (ctypes.c_int32, [_P]),
@@ -632,6 +635,31 @@ def fx_tune_time(tape: Tape, inputs, out, shape, kind, cfgs, ws=None, warmup=2, 
     check(lib().fx_tune_time(tape.handle, dt, arr, len(inputs), _shape(shape), kind, _ptr(out),
                              p, nb, carr, len(cfgs), warmup, reps, ms, _stream(stream)))
     return [[ms[c * reps + r] for r in range(reps)] for c in range(len(cfgs))]
+
+
+def fx_tune_grid(kind, dt) -> list:
+    """The autotuner's configuration grid (65 tuples, the default last)."""
+    n = lib().fx_tune_grid(kind, dt, None, 0)
+    if n < 0:
+        check(n)
+    arr = (Launch * n)()
+    check(min(0, lib().fx_tune_grid(kind, dt, arr, n)))
+    return [arr[i].as_tuple() for i in range(n)]
+
+
+def fx_autotune(tape: Tape, inputs, out, shape, kind=0, ws=None, warmup=2, reps=5, dt=None,
+                stream=None):
+    """Exhaustive search over fx_tune_grid: (best configuration, its median ms)."""
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    if dt is None:
+        dt = dtype_code(inputs[0]) if inputs else dtype_code(out)
+    best = Launch()
+    ms = ctypes.c_float()
+    p, nb = _ws(ws)
+    check(lib().fx_autotune(tape.handle, dt, arr, len(inputs), _shape(shape), kind, _ptr(out), p,
+                            nb, warmup, reps, ctypes.byref(best), ctypes.byref(ms),
+                            _stream(stream)))
+    return best.as_tuple(), ms.value
 
 
 # ---- learned cost model -------------------------------------------------------------------

@@ -142,3 +142,25 @@ def test_sixteen_slot_programs(dtype):
     _run(fx, torch, nodes, 4, 9, 0, dtype, (33333, 1), 0)
     _run(fx, torch, nodes, 4, 9, 0, dtype, (40001, 1), fx.R_ACCU)
     _run(fx, torch, nodes, 4, 9, 0, dtype, (129, 131), fx.R_COLSUM)
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+def test_native_autotune(kind):
+    # the exhaustive search returns a configuration of the grid, and the
+    # tape run under it matches the oracle
+    torch, fx = need_gpu()
+    from paper_2604_22242_amd.model import C2_NODES
+    shape = (4096, 96)
+    n = shape[0] * shape[1]
+    host, dev = tree_inputs(7, 1, 3, n, "f32")
+    tape = fx.Tape(C2_NODES)
+    out = empty(n if kind == 0 else shape[1], "f32")
+    ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda") if kind else None
+    best, ms = fx.fx_autotune(tape, dev, out, shape, kind, ws, warmup=1, reps=3)
+    assert best in fx.fx_tune_grid(kind, fx.F32)[:-1] and ms > 0
+    ws2 = fx.workspace(kind, fx.F32, shape, best) if kind else None
+    fx.fx_tape_eval(tape, dev, out, shape, kind, ws2, cfg=best)
+    torch.cuda.synchronize()
+    v, mu = oracle.evaluate(oracle_expr(C2_NODES), host, "f32", shape=shape,
+                            reduce=None if kind == 0 else "colsum")
+    assert_close(from_dev(out, "f32"), v, mu, "f32", "autotuned %s" % (best,))

@@ -57,3 +57,20 @@ def test_noise_summary_recovers_a_known_spread():
     rep = noise_summary([(1.0, 1.0), (2.0, 2.0), (float("nan"), 1.0), (0.0, 1.0)])
     assert rep["cells"] == 2 and rep["cv_estimate"] == 0.0 and rep["within_2pct"] == 1.0
     assert noise_summary([])["cells"] == 0
+
+
+def test_native_grid_matches_the_driver():
+    # the C library's grid (fx_autotune's search space) and the Python
+    # driver's are the same configurations in the same order; no device:
+    # 256 CUs assumed by both
+    import os
+    import paper_2604_22242_amd as fx
+    if not os.path.exists(fx.LIB_PATH):
+        from paper_2604_22242_amd import build
+        build.build()
+    from paper_2604_22242_amd import tune
+    kinds = {None: 0, "accu": fx.R_ACCU, "colsum": fx.R_COLSUM, "rowsum": fx.R_ROWSUM,
+             "norm": fx.R_NORM}
+    for red, kind in kinds.items():
+        for dt, code in (("f32", fx.F32), ("bf16", fx.BF16)):
+            assert fx.fx_tune_grid(kind, code) == [c for c, _ in tune.grid(red, dt)], (red, dt)
