@@ -536,6 +536,32 @@ int fx_model_choose(const fx_model* m, const float* features, int32_t* choice);
 
 void fx_model_destroy(fx_model* m);
 
+/* The model's 25 input features for tape t evaluated with storage dtype dt,
+ * shape `shape` and result kind `kind` (0 or FX_R_ACCU / COLSUM / ROWSUM /
+ * NORM), in training order: 8 operator counts (add, sub, schur, div, neg,
+ * abs, exp, sqrt); constants, depth, instructions, slots, inputs; 1 for
+ * 2-byte storage; log2 of size, rows and columns; the kind one-hot
+ * (element-wise, accu, column sums, row sums, norm); bytes per element
+ * (inputs, plus the output if element-wise); div + exp + sqrt count; log2
+ * of the bytes moved.  Writes them to out[0..cap) and returns 25 (only the
+ * count with out NULL or cap < 25); negative fx_status on bad arguments.
+ * Host only. */
+int32_t fx_tape_features(const fx_tape* t, fx_dtype dt, fx_shape shape, int kind, float* out,
+                         int32_t cap);
+
+/* Load a model file written by the Python driver's save ("FXM1": int32
+ * n_features, hidden, n_heads, head sizes; float means, standard
+ * deviations; int32 parameter count; float parameters) into a new model
+ * (device memory; fx_model_destroy frees it).  FX_E_ARG if the file is
+ * missing or malformed. */
+int fx_model_load(const char* path, fx_model** out);
+
+/* The launch configuration the model picks for one feature row: its four
+ * heads (block 4, EPT 2, vector 2, split 4 classes) mapped onto the
+ * autotuner's grid for `kind` and dt (fx_tune_grid), on the host. */
+int fx_model_predict(const fx_model* m, const float* features, int kind, fx_dtype dt,
+                     fx_launch* out);
+
 /* ---- measurement kernels ------------------------------------------------- */
 
 /* dst[i] = src[i] for `bytes` bytes (16-byte aligned, multiple of 16): the

@@ -145,6 +145,10 @@ _SIGS = {
     "fx_model_forward": (_I, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "fx_model_choose": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]),
     "fx_model_destroy": (None, [_P]),
+    "fx_tape_features": (ctypes.c_int32, [_P, _I, Shape, _I, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.c_int32]),
+    "fx_model_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "fx_model_predict": (_I, [_P, ctypes.POINTER(ctypes.c_float), _I, _I, _LP]),
     "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
     "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
     "fx_bw_write": (_I, [_P, _SZ, ctypes.c_uint32, _LP, _P]),
@@ -637,6 +641,15 @@ def fx_tune_time(tape: Tape, inputs, out, shape, kind, cfgs, ws=None, warmup=2, 
     return [[ms[c * reps + r] for r in range(reps)] for c in range(len(cfgs))]
 
 
+def fx_tape_features(tape: Tape, dt, shape, kind=0) -> list:
+    """The cost model's 25 features of `tape` at this dtype, shape and kind."""
+    out = (ctypes.c_float * 25)()
+    n = lib().fx_tape_features(tape.handle, dt, _shape(shape), kind, out, 25)
+    if n < 0:
+        check(n)
+    return [out[i] for i in range(n)]
+
+
 def fx_tune_grid(kind, dt) -> list:
     """The autotuner's configuration grid (65 tuples, the default last)."""
     n = lib().fx_tune_grid(kind, dt, None, 0)
@@ -716,6 +729,13 @@ class Model:
         check(lib().fx_model_choose(self.handle, x, out))
         return list(out)
 
+    def predict(self, features, kind, dt) -> tuple:
+        """The launch configuration the model picks (fx_model_predict)."""
+        x = (ctypes.c_float * self.n_features)(*[float(v) for v in features])
+        out = Launch()
+        check(lib().fx_model_predict(self.handle, x, kind, dt, ctypes.byref(out)))
+        return out.as_tuple()
+
     def destroy(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.fx_model_destroy(self.handle)
@@ -727,6 +747,23 @@ class Model:
 
 def fx_model_create(n_features, hidden, heads) -> Model:
     return Model(n_features, hidden, heads)
+
+
+def fx_model_load(path) -> Model:
+    """A model from its FXM1 file (the C loader; the header read here only
+    sizes the Python wrapper)."""
+    import struct
+    with open(path, "rb") as f:
+        head = f.read(16)
+        if len(head) < 16 or head[:4] != b"FXM1":
+            raise FxError(1, "%s is not a model file (FXM1)" % path)
+        F, H, nh = struct.unpack("<3i", head[4:16])
+        heads = struct.unpack("<%di" % nh, f.read(4 * nh)) if 0 < nh <= 8 else ()
+    m = Model.__new__(Model)
+    m.n_features, m.hidden, m.heads = F, H, tuple(heads)
+    m.handle = ctypes.c_void_p()
+    check(lib().fx_model_load(str(path).encode(), ctypes.byref(m.handle)))
+    return m
 
 
 def fx_model_num_params(m: Model) -> int:

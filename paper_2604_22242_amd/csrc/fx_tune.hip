@@ -2,6 +2,8 @@
 // configurations with HIP events on the caller's stream, the configuration
 // grid, and the exhaustive search over it.
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -10,6 +12,11 @@
 
 using namespace fx;
 
+extern "C" int fx_model_create(int32_t n_features, int32_t hidden, const int32_t* head_sizes,
+                               int32_t n_heads, fx_model** out);
+extern "C" int fx_model_set(fx_model* m, const float* params, const float* mean, const float* stdv);
+extern "C" int fx_model_choose(const fx_model* m, const float* features, int32_t* choice);
+extern "C" void fx_model_destroy(fx_model* m);
 extern "C" int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs,
                             int32_t n_inputs, fx_shape s, int kind, void* out, void* ws,
                             size_t ws_bytes, const fx_launch* cfg, void* stream);
@@ -138,5 +145,103 @@ extern "C" int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inp
   if (arg < 0) return fail(FX_E_UNSUPPORTED, "no configuration of the grid runs this tape");
   *best = grid[arg];
   *best_ms = lo;
+  return FX_OK;
+}
+
+// ---- the learned model, natively -------------------------------------------
+//
+// Features of a tape (the model's 25 inputs, in the order the model was
+// trained on): the 8 operator counts (add, sub, schur, div, neg, abs, exp,
+// sqrt); constants, depth, instructions, slots, inputs; 1 for 2-byte
+// storage; log2 of the size, rows and columns; the result kind one-hot
+// (element-wise, accu, column sums, row sums, norm); bytes per element
+// (inputs plus the output of an element-wise result); the transcendental
+// count (div + exp + sqrt); log2 of the bytes moved.
+
+constexpr int kModelFeatures = 25;
+
+extern "C" int32_t fx_tape_features(const fx_tape* t, fx_dtype dt, fx_shape shape, int kind,
+                                    float* out, int32_t cap) {
+  if (!t) return fail(FX_E_ARG, "NULL tape");
+  const int elem = elem_of(dt);
+  if (!elem) return fail(FX_E_DTYPE, "tapes take floating-point dtypes");
+  if (kind < 0 || kind > FX_R_NORM || kind == FX_R_DOT) return fail(FX_E_ARG, "unknown kind %d", kind);
+  if (shape.n_rows < 0 || shape.n_cols < 0) return fail(FX_E_ARG, "negative shape");
+  if (!out || cap < kModelFeatures) return kModelFeatures;
+  const fx_tape_info& I = t->info;
+  const double rows = (double)shape.n_rows, cols = (double)shape.n_cols;
+  const double n = std::max(1.0, rows * cols);
+  const double bpe = (double)elem * (I.n_inputs + (kind == 0 ? 1 : 0));
+  int k = 0;
+  for (int q = 0; q < 8; ++q) out[k++] = (float)I.op_count[q];
+  out[k++] = (float)I.n_consts;
+  out[k++] = (float)I.depth;
+  out[k++] = (float)I.n_instructions;
+  out[k++] = (float)I.n_slots;
+  out[k++] = (float)I.n_inputs;
+  out[k++] = elem == 2 ? 1.0f : 0.0f;
+  out[k++] = (float)log2(n);
+  out[k++] = (float)log2(std::max(1.0, rows));
+  out[k++] = (float)log2(std::max(1.0, cols));
+  const int onehot[5] = {0, FX_R_ACCU, FX_R_COLSUM, FX_R_ROWSUM, FX_R_NORM};
+  for (int r : onehot) out[k++] = kind == r ? 1.0f : 0.0f;
+  out[k++] = (float)bpe;
+  out[k++] = (float)(I.op_count[3] + I.op_count[6] + I.op_count[7]);
+  out[k++] = (float)log2(std::max(1.0, bpe * n));
+  return k;
+}
+
+// The model file: "FXM1", int32 n_features, hidden, n_heads, head sizes,
+// float mean[n_features], std[n_features], int32 n_params, float params.
+extern "C" int fx_model_load(const char* path, fx_model** out) {
+  if (!path || !out) return fail(FX_E_ARG, "NULL argument");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(FX_E_ARG, "cannot open %s", path);
+  auto rd = [&](void* p, size_t bytes) { return fread(p, 1, bytes, f) == bytes; };
+  char magic[4];
+  int32_t F = 0, H = 0, nh = 0, heads[8], np = 0;
+  bool ok = rd(magic, 4) && memcmp(magic, "FXM1", 4) == 0 && rd(&F, 4) && rd(&H, 4) && rd(&nh, 4) &&
+            F > 0 && F <= 64 && H > 0 && H <= 256 && nh > 0 && nh <= 8 && rd(heads, 4 * (size_t)nh);
+  int32_t C = 0;
+  for (int h = 0; ok && h < nh; ++h) {
+    ok = heads[h] >= 2;
+    C += heads[h];
+  }
+  std::vector<float> mean(ok ? F : 0), stdv(ok ? F : 0), params;
+  ok = ok && rd(mean.data(), 4 * (size_t)F) && rd(stdv.data(), 4 * (size_t)F) && rd(&np, 4) &&
+       np == H * F + H + C * H + C;
+  if (ok) {
+    params.resize(np);
+    ok = rd(params.data(), 4 * (size_t)np);
+  }
+  fclose(f);
+  if (!ok) return fail(FX_E_ARG, "%s is not a model file (FXM1) of valid dimensions", path);
+  fx_model* m = nullptr;
+  if (int rc = fx_model_create(F, H, heads, nh, &m)) return rc;
+  if (int rc = fx_model_set(m, params.data(), mean.data(), stdv.data())) {
+    fx_model_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return FX_OK;
+}
+
+// The model's classes onto the grid: heads block / EPT / vector / split.
+extern "C" int fx_model_predict(const fx_model* m, const float* features, int kind, fx_dtype dt,
+                                fx_launch* out) {
+  if (!m || !features || !out) return fail(FX_E_ARG, "NULL argument");
+  const int elem = elem_of(dt);
+  if (!elem) return fail(FX_E_DTYPE, "tapes take floating-point dtypes");
+  if (kind < 0 || kind > FX_R_NORM || kind == FX_R_DOT) return fail(FX_E_ARG, "unknown kind %d", kind);
+  int32_t choice[8] = {0};
+  if (int rc = fx_model_choose(m, features, choice)) return rc;
+  if (choice[0] < 0 || choice[0] > 3 || choice[1] < 0 || choice[1] > 1 || choice[2] < 0 ||
+      choice[2] > 1 || choice[3] < 0 || choice[3] > 3)
+    return fail(FX_E_ARG, "the model's heads are not block (4) / EPT (2) / vector (2) / split (4)");
+  int sp[4];
+  grid_splits(kind, device_cus(), sp);
+  *out = fx_launch{kGridBlocks[choice[0]], kGridEpts[choice[1]], choice[2] ? 16 : elem,
+                   sp[choice[3]]};
   return FX_OK;
 }

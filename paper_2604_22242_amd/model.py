@@ -73,12 +73,25 @@ def train(records, hidden=HIDDEN, epochs=400, batch=256, lr=2e-3, seed=0, verbos
     return m, curve
 
 
+def write_fxm(path: str, n_features, hidden, heads, mean, std, params):
+    """The self-contained model file the C loader reads (fx_model_load):
+    "FXM1", int32 n_features, hidden, n_heads, head sizes; float32 means,
+    standard deviations; int32 parameter count; float32 parameters."""
+    import struct
+    with open(path, "wb") as f:
+        f.write(b"FXM1" + struct.pack("<3i", n_features, hidden, len(heads)))
+        f.write(struct.pack("<%di" % len(heads), *heads))
+        f.write(np.asarray(mean, np.float32).tobytes() + np.asarray(std, np.float32).tobytes())
+        f.write(struct.pack("<i", len(params)) + np.asarray(params, np.float32).tobytes())
+
+
 def save(m: Model, path: str):
     params, mean, std = m.get()
     params.tofile(path + ".bin")
     json.dump({"n_features": m.n_features, "hidden": m.hidden, "heads": list(m.heads),
                "features": FEATURES, "mean": mean.tolist(), "std": std.tolist()},
               open(path + ".json", "w"), indent=1)
+    write_fxm(path + ".fxm", m.n_features, m.hidden, m.heads, mean, std, params)
 
 
 def load(path: str) -> Model:

@@ -214,3 +214,33 @@ def test_committed_model_drives_tapes():
         half = dt if (kind == 0 and dt == "bf16") else None
         assert_close(from_dev(out, od), v, mu, dt, "model-picked %s item %d" % (cfg, it["id"]),
                      out_dtype=half)
+
+
+def test_native_loader_and_predictor_agree_with_the_driver():
+    """fx_model_load reads the committed FXM1 file; fx_tape_features and
+    fx_model_predict give, for held-out tuning items of every kind, the same
+    launch configuration as the Python driver (JSON + parameter files,
+    features() and config_of())."""
+    torch, fx = need_gpu()
+    import os
+    from paper_2604_22242_amd import model, tune
+    from synth import trees
+    base = os.path.join(os.path.dirname(fx.LIB_PATH), "launch_model")
+    native = fx.fx_model_load(base + ".fxm")
+    driver = model.load(base)
+    assert native.heads == driver.heads and native.n_features == driver.n_features
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    kinds = {None: 0, "accu": fx.R_ACCU, "colsum": fx.R_COLSUM, "rowsum": fx.R_ROWSUM,
+             "norm": fx.R_NORM}
+    for i in range(60):
+        it = trees.tuning_item(6, i)
+        tape = fx.Tape(it["nodes"])
+        code = fx.F32 if it["dtype"] == "f32" else fx.BF16
+        f = fx.fx_tape_features(tape, code, it["shape"], kinds[it["reduce"]])
+        got = native.predict(f, kinds[it["reduce"]], code)
+        want = model.config_of(tuple(driver.choose(tune.features(tape.info(), it["dtype"], it["shape"],
+                                                                 it["reduce"]))),
+                               it["reduce"], it["dtype"], cus)
+        assert got == tuple(want), (i, got, want)
+    with pytest.raises(fx.FxError):
+        fx.fx_model_load(base + ".json")          # not a model file

@@ -74,3 +74,44 @@ def test_native_grid_matches_the_driver():
     for red, kind in kinds.items():
         for dt, code in (("f32", fx.F32), ("bf16", fx.BF16)):
             assert fx.fx_tune_grid(kind, code) == [c for c, _ in tune.grid(red, dt)], (red, dt)
+
+
+def test_native_features_match_the_driver():
+    # fx_tape_features (C, host only) and the driver's features() give the
+    # model the same inputs, for generated trees of every kind and both
+    # storage types
+    import numpy as np
+    import paper_2604_22242_amd as fx
+    from paper_2604_22242_amd import tune
+    codes = {"f32": fx.F32, "bf16": fx.BF16}
+    kinds = {None: 0, "accu": fx.R_ACCU, "colsum": fx.R_COLSUM, "rowsum": fx.R_ROWSUM,
+             "norm": fx.R_NORM}
+    for i in range(40):
+        item = trees.tuning_item(5, i)
+        tape = fx.Tape(item["nodes"])
+        got = fx.fx_tape_features(tape, codes[item["dtype"]], item["shape"], kinds[item["reduce"]])
+        want = tune.features(tape.info(), item["dtype"], item["shape"], item["reduce"])
+        assert np.array_equal(np.float32(got), np.float32(want)), (i, got, want)
+
+
+def test_model_file_layout(tmp_path):
+    # the FXM1 file the C loader reads: header, standardisation, parameters
+    import struct
+    import numpy as np
+    from paper_2604_22242_amd import model
+    p = tmp_path / "m.fxm"
+    model.write_fxm(str(p), 3, 2, (2, 2), [1, 2, 3], [4, 5, 6], np.arange(16, dtype=np.float32))
+    b = p.read_bytes()
+    assert b[:4] == b"FXM1" and struct.unpack("<5i", b[4:24]) == (3, 2, 2, 2, 2)
+    assert struct.unpack("<6f", b[24:48]) == (1, 2, 3, 4, 5, 6)
+    assert struct.unpack("<i", b[48:52]) == (16,) and len(b) == 52 + 64
+    # the committed model's file matches its parameter and JSON files
+    import json, os
+    base = os.path.join(os.path.dirname(model.__file__), "launch_model")
+    meta = json.load(open(base + ".json"))
+    c = open(base + ".fxm", "rb").read()
+    F, H, nh = struct.unpack("<3i", c[4:16])
+    assert (F, H, list(struct.unpack("<%di" % nh, c[16:16 + 4 * nh]))) == (
+        meta["n_features"], meta["hidden"], meta["heads"])
+    params = np.fromfile(base + ".bin", np.float32)
+    assert c.endswith(params.tobytes())
