@@ -488,10 +488,20 @@ int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t cap);
  * and its median time in *best_ms.  The default configuration is timed but
  * never chosen.  Configurations whose workspace exceeds ws_bytes, or that
  * are not compiled, are skipped; FX_E_UNSUPPORTED if none runs.
- * Synchronous. */
+ *
+ * db_path (may be NULL): a timing database, one JSON object per line, that
+ * the search appends its item to: "key" (a hash of the program with shape,
+ * dtype and kind), "dtype", "reduce" (null for element-wise), "shape",
+ * "cus", "features" (the 25 of fx_tape_features), "ms" (every grid
+ * configuration's median in grid order, null where it did not run),
+ * "best" (grid index), "best_ms", "default_ms", "mode" ("native") and
+ * "tune_seconds".  The learned model trains on such lines.  FX_E_ARG if
+ * the file cannot be opened or written (the search's results are still
+ * returned).  Synchronous. */
 int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                 fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes, int32_t warmup,
-                int32_t reps, fx_launch* best, float* best_ms, void* stream);
+                int32_t reps, fx_launch* best, float* best_ms, const char* db_path,
+                void* stream);
 
 /* The learned cost model: a two-layer perceptron (standardised features ->
  * hidden ReLU layer -> one softmax head per launch knob), trained on the

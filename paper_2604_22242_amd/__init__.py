@@ -134,7 +134,8 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_float), _P]),
     "fx_tune_grid": (ctypes.c_int32, [_I, _I, _LP, ctypes.c_int32]),
     "fx_autotune": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
-                         ctypes.c_int32, ctypes.c_int32, _LP, ctypes.POINTER(ctypes.c_float), _P]),
+                         ctypes.c_int32, ctypes.c_int32, _LP, ctypes.POINTER(ctypes.c_float),
+                         ctypes.c_char_p, _P]),
     "fx_model_create": (_I, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                              ctypes.c_int32, ctypes.POINTER(_P)]),
     "fx_model_num_params": (ctypes.c_int32, [_P]),
@@ -661,8 +662,10 @@ def fx_tune_grid(kind, dt) -> list:
 
 
 def fx_autotune(tape: Tape, inputs, out, shape, kind=0, ws=None, warmup=2, reps=5, dt=None,
-                stream=None):
-    """Exhaustive search over fx_tune_grid: (best configuration, its median ms)."""
+                db=None, stream=None):
+    """Exhaustive search over fx_tune_grid: (best configuration, its median
+    ms).  With `db` (a path), the search's record is appended to that JSON
+    lines timing database."""
     arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
     if dt is None:
         dt = dtype_code(inputs[0]) if inputs else dtype_code(out)
@@ -671,7 +674,7 @@ def fx_autotune(tape: Tape, inputs, out, shape, kind=0, ws=None, warmup=2, reps=
     p, nb = _ws(ws)
     check(lib().fx_autotune(tape.handle, dt, arr, len(inputs), _shape(shape), kind, _ptr(out), p,
                             nb, warmup, reps, ctypes.byref(best), ctypes.byref(ms),
-                            _stream(stream)))
+                            None if db is None else os.fsencode(db), _stream(stream)))
     return best.as_tuple(), ms.value
 
 

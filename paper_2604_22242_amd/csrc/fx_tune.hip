@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 #include "fx_tape.hpp"
@@ -120,31 +121,110 @@ extern "C" int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t c
   return k;
 }
 
+namespace {
+
+// A 64-bit FNV-1a hash of a tape's program (opcodes, slots, immediates),
+// storage dtype, shape and kind: the database key of a tuned item.
+uint64_t tape_key(const fx_tape* t, fx_dtype dt, fx_shape shape, int kind) {
+  const int32_t n = fx_tape_program(t, nullptr, nullptr, nullptr, nullptr, 0);
+  std::vector<uint16_t> op(n);
+  std::vector<uint8_t> s1(n), s2(n);
+  std::vector<double> imm(n);
+  fx_tape_program(t, op.data(), s1.data(), s2.data(), imm.data(), n);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t bytes) {
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ ((const uint8_t*)p)[i]) * 1099511628211ull;
+  };
+  mix(op.data(), op.size() * sizeof(uint16_t));
+  mix(s1.data(), s1.size());
+  mix(s2.data(), s2.size());
+  mix(imm.data(), imm.size() * sizeof(double));
+  const int64_t tail[4] = {(int64_t)dt, shape.n_rows, shape.n_cols, kind};
+  mix(tail, sizeof(tail));
+  return h;
+}
+
+const char* dtype_name(fx_dtype dt) {
+  switch (dt) {
+    case FX_F32: return "f32";
+    case FX_F64: return "f64";
+    case FX_BF16: return "bf16";
+    default: return "f16";
+  }
+}
+
+const char* kind_name(int kind) {
+  switch (kind) {
+    case FX_R_ACCU: return "accu";
+    case FX_R_COLSUM: return "colsum";
+    case FX_R_ROWSUM: return "rowsum";
+    case FX_R_NORM: return "norm";
+    default: return nullptr;  // element-wise
+  }
+}
+
+// Append one JSON line: the tuned item's features, every configuration's
+// median time (null where it did not run), the argmin and the default's time.
+int append_record(const char* path, const fx_tape* t, fx_dtype dt, fx_shape shape, int kind,
+                  const float* med, int n, int arg, double seconds) {
+  float feat[32];
+  const int nf = fx_tape_features(t, dt, shape, kind, feat, 32);
+  if (nf < 0) return -nf;
+  FILE* f = fopen(path, "a");
+  if (!f) return fail(FX_E_ARG, "cannot open %s for appending", path);
+  const char* kn = kind_name(kind);
+  fprintf(f, "{\"key\": \"%016llx:%lldx%lld:%s:%s\", \"dtype\": \"%s\", \"reduce\": ",
+          (unsigned long long)tape_key(t, dt, shape, kind), (long long)shape.n_rows,
+          (long long)shape.n_cols, dtype_name(dt), kn ? kn : "None", dtype_name(dt));
+  if (kn) fprintf(f, "\"%s\"", kn);
+  else fprintf(f, "null");
+  fprintf(f, ", \"shape\": [%lld, %lld], \"cus\": %d, \"features\": [",
+          (long long)shape.n_rows, (long long)shape.n_cols, device_cus());
+  for (int i = 0; i < nf; ++i) fprintf(f, "%s%.4g", i ? ", " : "", feat[i]);
+  fprintf(f, "], \"ms\": [");
+  for (int c = 0; c < n; ++c) {
+    if (isnan(med[c])) fprintf(f, "%snull", c ? ", " : "");
+    else fprintf(f, "%s%.4g", c ? ", " : "", med[c]);
+  }
+  fprintf(f, "], \"best\": %d, \"best_ms\": %.9g, \"default_ms\": %.9g, "
+          "\"mode\": \"native\", \"tune_seconds\": %.4f}\n",
+          arg, med[arg], med[n - 1], seconds);
+  const bool bad = ferror(f) != 0;
+  if (fclose(f) != 0 || bad) return fail(FX_E_ARG, "writing %s failed", path);
+  return FX_OK;
+}
+
+}  // namespace
+
 extern "C" int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inputs,
                            int32_t n_inputs, fx_shape shape, int kind, void* out, void* ws,
                            size_t ws_bytes, int32_t warmup, int32_t reps, fx_launch* best,
-                           float* best_ms, void* stream) {
+                           float* best_ms, const char* db_path, void* stream) {
   if (!t || !best || !best_ms || warmup < 0 || reps <= 0) return fail(FX_E_ARG, "bad arguments");
+  const auto t0 = std::chrono::steady_clock::now();
   fx_launch grid[kGridSize];
   const int32_t n = fx_tune_grid(kind, dt, grid, kGridSize);
   if (n < 0) return n;
-  std::vector<float> ms((size_t)n * reps);
+  std::vector<float> ms((size_t)n * reps), med(n);
   if (int rc = fx_tune_time(t, dt, inputs, n_inputs, shape, kind, out, ws, ws_bytes, grid, n,
                             warmup, reps, ms.data(), stream))
     return rc;
-  int arg = -1;
-  float lo = INFINITY;
-  for (int c = 0; c + 1 < n; ++c) {  // the default (last) is timed, never chosen
+  for (int c = 0; c < n; ++c) {
     float* row = ms.data() + (size_t)c * reps;
     bool ok = true;
     for (int r = 0; r < reps; ++r) ok = ok && !isnan(row[r]);
-    if (!ok) continue;
-    const float m = median_of(row, reps);
-    if (m < lo) { lo = m; arg = c; }
+    med[c] = ok ? median_of(row, reps) : NAN;
   }
+  int arg = -1;
+  for (int c = 0; c + 1 < n; ++c)  // the default (last) is timed, never chosen
+    if (!isnan(med[c]) && (arg < 0 || med[c] < med[arg])) arg = c;
   if (arg < 0) return fail(FX_E_UNSUPPORTED, "no configuration of the grid runs this tape");
   *best = grid[arg];
-  *best_ms = lo;
+  *best_ms = med[arg];
+  if (db_path) {
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return append_record(db_path, t, dt, shape, kind, med.data(), n, arg, sec);
+  }
   return FX_OK;
 }
 

@@ -145,7 +145,7 @@ def test_sixteen_slot_programs(dtype):
 
 
 @pytest.mark.parametrize("kind", [0, 2])
-def test_native_autotune(kind):
+def test_native_autotune(kind, tmp_path):
     # the exhaustive search returns a configuration of the grid, and the
     # tape run under it matches the oracle
     torch, fx = need_gpu()
@@ -156,8 +156,26 @@ def test_native_autotune(kind):
     tape = fx.Tape(C2_NODES)
     out = empty(n if kind == 0 else shape[1], "f32")
     ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda") if kind else None
-    best, ms = fx.fx_autotune(tape, dev, out, shape, kind, ws, warmup=1, reps=3)
-    assert best in fx.fx_tune_grid(kind, fx.F32)[:-1] and ms > 0
+    db = tmp_path / "tune.jsonl"
+    best, ms = fx.fx_autotune(tape, dev, out, shape, kind, ws, warmup=1, reps=3, db=db)
+    grid = fx.fx_tune_grid(kind, fx.F32)
+    assert best in grid[:-1] and ms > 0
+    # the appended database line names the same argmin, with the tape's
+    # features, and the trainer reads it
+    import json
+    from paper_2604_22242_amd.model import dataset
+    from paper_2604_22242_amd.tune import load_db, record_grid
+    (rec,) = load_db(str(db)).values()
+    assert rec["mode"] == "native" and rec["reduce"] == (None if kind == 0 else "colsum")
+    assert rec["shape"] == list(shape) and len(rec["ms"]) == len(grid)
+    assert grid[rec["best"]] == best and abs(rec["best_ms"] - ms) <= 1e-6 * ms
+    assert rec["ms"][rec["best"]] == min(x for x in rec["ms"][:-1] if x is not None)
+    assert rec["features"] == [float("%.4g" % f) for f in
+                               fx.fx_tape_features(tape, fx.F32, shape, kind)]
+    assert record_grid(rec)[rec["best"]][0] == best
+    X, Y = dataset([rec])
+    assert X.shape == (1, 25) and Y.shape == (1, 4)
+    json.loads(db.read_text().splitlines()[0])
     ws2 = fx.workspace(kind, fx.F32, shape, best) if kind else None
     fx.fx_tape_eval(tape, dev, out, shape, kind, ws2, cfg=best)
     torch.cuda.synchronize()
