@@ -530,6 +530,19 @@ int fx_model_get(fx_model* m, float* params, float* mean, float* stdv);
 int fx_model_train_step(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
                         float lr, float* d_loss, void* stream);
 
+/* Train for `epochs` passes over the n device rows d_X [n x F] / d_labels
+ * [n x n_heads] in mini-batches of `batch` rows (the last of an epoch may be
+ * shorter), one fx_model_train_step each.  Epoch e visits the rows in the
+ * order perm[e*n .. e*n + n): a HOST int32 array, each epoch a permutation
+ * of 0..n-1 (checked: FX_E_ARG otherwise); NULL visits them in order.
+ * d_losses (device FP32 [epochs], may be NULL) gets each epoch's last
+ * mini-batch loss.  Waits for the stream's earlier work and the copy of
+ * perm, then enqueues the steps on `stream` and returns.  Calls on one
+ * model must not overlap. */
+int fx_model_train(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t n,
+                   int32_t epochs, int32_t batch, float lr, const int32_t* perm,
+                   float* d_losses, void* stream);
+
 /* The gradient of the mean cross-entropy (no update) into d_grad [params]. */
 int fx_model_grad(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
                   float* d_grad, float* d_loss, void* stream);

@@ -142,6 +142,8 @@ _SIGS = {
     "fx_model_set": (_I, [_P, _P, _P, _P]),
     "fx_model_get": (_I, [_P, _P, _P, _P]),
     "fx_model_train_step": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P]),
+    "fx_model_train": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_float, _P, _P, _P]),
     "fx_model_grad": (_I, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "fx_model_forward": (_I, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "fx_model_choose": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]),
@@ -717,6 +719,23 @@ class Model:
     def train_step(self, X, labels, lr, loss=None, stream=None):
         return check(lib().fx_model_train_step(self.handle, _ptr(X), _ptr(labels), X.shape[0],
                                                float(lr), _ptr(loss), _stream(stream)))
+
+    def train(self, X, labels, epochs, batch, lr, perm=None, losses=None, stream=None):
+        """fx_model_train: `epochs` passes over the device rows X / labels in
+        mini-batches, epoch e visiting rows perm[e] (host int32 array of
+        shape [epochs, n]; None = natural order).  losses: device FP32
+        [epochs] or None."""
+        n = X.shape[0]
+        p = None
+        if perm is not None:
+            import numpy as np
+            perm = np.ascontiguousarray(perm, dtype=np.int32)
+            if perm.shape != (epochs, n):
+                raise ValueError("perm must have shape (epochs, n)")
+            p = perm.ctypes.data_as(ctypes.c_void_p)
+        return check(lib().fx_model_train(self.handle, _ptr(X), _ptr(labels), n, epochs, batch,
+                                          lr, p, _ptr(losses) if losses is not None else None,
+                                          _stream(stream)))
 
     def grad(self, X, labels, grad, loss=None, stream=None):
         return check(lib().fx_model_grad(self.handle, _ptr(X), _ptr(labels), X.shape[0],

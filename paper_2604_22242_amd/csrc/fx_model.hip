@@ -7,7 +7,8 @@
 // cores to matter).
 //
 // Kernels:
-//   k_mlp_rows    one block per batch row: forward, loss, dlogits, dh
+//   k_mlp_rows    one block per batch row: forward, loss, dlogits, dh (the
+//                 batch's rows optionally gathered through an index list)
 //   k_mlp_params  one thread per parameter: gradient summed over the batch
 //                 in row order (deterministic), then the Adam update
 //   k_mlp_predict one block per row: forward and per-head argmax
@@ -59,7 +60,8 @@ __device__ void mlp_row_forward(const mlp_dims& d, const float* __restrict__ x,
 }
 
 __global__ __launch_bounds__(256) void k_mlp_rows(mlp_dims d, const float* __restrict__ X,
-                                                const int32_t* __restrict__ labels, int B,
+                                                const int32_t* __restrict__ labels,
+                                                const int32_t* __restrict__ rows, int B,
                                                 const float* __restrict__ mean,
                                                 const float* __restrict__ stdv,
                                                 const float* __restrict__ P, float* __restrict__ XN,
@@ -68,7 +70,8 @@ __global__ __launch_bounds__(256) void k_mlp_rows(mlp_dims d, const float* __res
   __shared__ float xn[kMlpMaxF], h[kMlpMaxH], logit[kMlpMaxC], dl[kMlpMaxC];
   __shared__ float head_loss[kMlpMaxHeads];
   const int b = blockIdx.x, t = threadIdx.x;
-  mlp_row_forward(d, X + (size_t)b * d.F, mean, stdv, P, xn, h, logit);
+  const size_t r = rows ? (size_t)rows[b] : (size_t)b;  // batch row b is data row r
+  mlp_row_forward(d, X + r * d.F, mean, stdv, P, xn, h, logit);
   // per-head softmax cross-entropy: loss = log sum exp(logits) - logit[y];
   // dlogits = (softmax - onehot(y)) / B
   if (t < d.n_heads) {
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(256) void k_mlp_rows(mlp_dims d, const float* __res
     for (int c = 1; c < k; ++c) m = fmaxf(m, logit[o + c]);
     float z = 0.f;
     for (int c = 0; c < k; ++c) z += expf(logit[o + c] - m);
-    const int y = min(max(labels[(size_t)b * d.n_heads + t], 0), k - 1);
+    const int y = min(max(labels[r * d.n_heads + t], 0), k - 1);
     for (int c = 0; c < k; ++c) {
       const float p = expf(logit[o + c] - m) / z;
       dl[o + c] = (p - (c == y ? 1.f : 0.f)) / (float)B;
@@ -174,6 +177,8 @@ struct fx_model {
   float* dStd = nullptr;
   float* scratch = nullptr;  // XN, Hs, DL, DH, row_loss for `cap` rows
   int cap = 0;
+  int32_t* perm = nullptr;  // fx_model_train's visiting order, `perm_cap` entries
+  size_t perm_cap = 0;
   long step = 0;
   std::vector<float> hP, hMean, hStd;  // host twin for single queries
 };
@@ -187,6 +192,7 @@ static void model_free(fx_model* m) {
   (void)hipFree(m->dMean);
   (void)hipFree(m->dStd);
   (void)hipFree(m->scratch);
+  (void)hipFree(m->perm);
 }
 
 static int ensure_scratch(fx_model* m, int B) {
@@ -295,9 +301,10 @@ int fx_model_get(fx_model* m, float* params, float* mean, float* stdv) {
 }
 
 // Gradient (lr = 0) or one Adam step over a batch of B rows in device memory.
-static int model_step(fx_model* m, const float* X, const int32_t* labels, int32_t B, float lr,
-                      float beta1, float beta2, float eps, float* d_loss, float* d_grad,
-                      hipStream_t st) {
+// `rows` (device, may be NULL) lists the B data rows of the batch.
+static int model_step(fx_model* m, const float* X, const int32_t* labels, const int32_t* rows,
+                      int32_t B, float lr, float beta1, float beta2, float eps, float* d_loss,
+                      float* d_grad, hipStream_t st) {
   if (!m || !X || !labels || B <= 0) return fail(FX_E_ARG, "bad arguments");
   if (int rc = ensure_scratch(m, B)) return rc;
   const mlp_dims& d = m->d;
@@ -307,8 +314,8 @@ static int model_step(fx_model* m, const float* X, const int32_t* labels, int32_
   float* DH = DL + (size_t)B * d.C;
   float* RL = DH + (size_t)B * d.H;
   const int threads = std::max(64, ((std::max(d.H, std::max(d.F, d.C)) + 63) / 64) * 64);
-  hipLaunchKernelGGL(k_mlp_rows, dim3(B), dim3(threads), 0, st, d, X, labels, B, m->dMean, m->dStd,
-                     m->dP, XN, Hs, DL, DH, RL);
+  hipLaunchKernelGGL(k_mlp_rows, dim3(B), dim3(threads), 0, st, d, X, labels, rows, B, m->dMean,
+                     m->dStd, m->dP, XN, Hs, DL, DH, RL);
   double c1 = 1.0, c2 = 1.0;
   if (lr != 0.f) {
     m->step += 1;
@@ -325,13 +332,67 @@ static int model_step(fx_model* m, const float* X, const int32_t* labels, int32_
 int fx_model_train_step(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
                         float lr, float* d_loss, void* stream) {
   if (!(lr > 0.f)) return fail(FX_E_ARG, "learning rate must be positive");
-  return model_step(m, d_X, d_labels, batch, lr, 0.9f, 0.999f, 1e-8f, d_loss, nullptr, S(stream));
+  return model_step(m, d_X, d_labels, nullptr, batch, lr, 0.9f, 0.999f, 1e-8f, d_loss, nullptr,
+                    S(stream));
+}
+
+int fx_model_train(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t n,
+                   int32_t epochs, int32_t batch, float lr, const int32_t* perm,
+                   float* d_losses, void* stream) {
+  if (!m || !d_X || !d_labels || n <= 0 || epochs < 0 || batch <= 0)
+    return fail(FX_E_ARG, "bad arguments");
+  if (!(lr > 0.f)) return fail(FX_E_ARG, "learning rate must be positive");
+  if (epochs == 0) return FX_OK;
+  const size_t total = (size_t)epochs * n;
+  if (perm) {  // every epoch's order must be a permutation of 0..n-1
+    std::vector<uint8_t> seen(n);
+    for (int32_t e = 0; e < epochs; ++e) {
+      std::fill(seen.begin(), seen.end(), 0);
+      for (int32_t i = 0; i < n; ++i) {
+        const int32_t r = perm[(size_t)e * n + i];
+        if (r < 0 || r >= n || seen[r]) return fail(FX_E_ARG, "epoch %d order is not a permutation", e);
+        seen[r] = 1;
+      }
+    }
+  }
+  hipStream_t st = S(stream);
+  if (total > m->perm_cap) {
+    (void)hipFree(m->perm);
+    m->perm = nullptr;
+    m->perm_cap = 0;
+    if (int rc = hip_check(hipMalloc((void**)&m->perm, total * sizeof(int32_t)), "hipMalloc"))
+      return rc;
+    m->perm_cap = total;
+  }
+  std::vector<int32_t> natural;
+  const int32_t* src = perm;
+  if (!src) {
+    natural.resize(total);
+    for (size_t i = 0; i < total; ++i) natural[i] = (int32_t)(i % (size_t)n);
+    src = natural.data();
+  }
+  // The order buffer belongs to the model: the copy is queued behind the
+  // stream's earlier work, and waited for before the host array can go.
+  if (int rc = hip_check(hipMemcpyAsync(m->perm, src, total * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, st), "hipMemcpyAsync"))
+    return rc;
+  if (int rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize")) return rc;
+  for (int32_t e = 0; e < epochs; ++e)
+    for (int32_t s = 0; s < n; s += batch) {
+      const int32_t b = std::min(batch, n - s);
+      const bool last = s + b >= n;
+      if (int rc = model_step(m, d_X, d_labels, m->perm + (size_t)e * n + s, b, lr, 0.9f, 0.999f,
+                              1e-8f, last && d_losses ? d_losses + e : nullptr, nullptr, st))
+        return rc;
+    }
+  return FX_OK;
 }
 
 int fx_model_grad(fx_model* m, const float* d_X, const int32_t* d_labels, int32_t batch,
                   float* d_grad, float* d_loss, void* stream) {
   if (!d_grad) return fail(FX_E_ARG, "NULL gradient output");
-  return model_step(m, d_X, d_labels, batch, 0.f, 0.9f, 0.999f, 1e-8f, d_loss, d_grad, S(stream));
+  return model_step(m, d_X, d_labels, nullptr, batch, 0.f, 0.9f, 0.999f, 1e-8f, d_loss, d_grad,
+                    S(stream));
 }
 
 int fx_model_forward(const fx_model* m, const float* d_X, int32_t batch, float* d_logits,

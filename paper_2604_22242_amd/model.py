@@ -55,20 +55,16 @@ def train(records, hidden=HIDDEN, epochs=400, batch=256, lr=2e-3, seed=0, verbos
     m.set(init_params(X.shape[1], hidden, sum(HEADS), seed), mean, std)
     Xd = torch.from_numpy(X).cuda()
     Yd = torch.from_numpy(Y).cuda()
-    loss = torch.zeros(1, device="cuda")
     rng = np.random.default_rng(seed + 1)
     n = X.shape[0]
-    curve = []
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(n)).cuda()
-        Xp, Yp = Xd[perm].contiguous(), Yd[perm].contiguous()
-        for s in range(0, n, batch):
-            m.train_step(Xp[s:s + batch], Yp[s:s + batch], lr, loss)
-        if ep % 50 == 0 or ep == epochs - 1:
-            torch.cuda.synchronize()
-            curve.append((ep, float(loss.item())))
-            if verbose:
-                print("epoch %d loss %.4f" % curve[-1], flush=True)
+    perm = np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+    losses = torch.zeros(max(1, epochs), device="cuda")
+    m.train(Xd, Yd, epochs, batch, lr, perm, losses)  # the whole loop in fx_model_train
+    losses = losses.cpu().tolist()
+    curve = [(ep, losses[ep]) for ep in range(epochs) if ep % 50 == 0 or ep == epochs - 1]
+    if verbose:
+        for c in curve:
+            print("epoch %d loss %.4f" % c, flush=True)
     m.get()  # refresh the host twin
     return m, curve
 

@@ -244,3 +244,58 @@ def test_native_loader_and_predictor_agree_with_the_driver():
         assert got == tuple(want), (i, got, want)
     with pytest.raises(fx.FxError):
         fx.fx_model_load(base + ".json")          # not a model file
+
+
+def test_native_training_loop_equals_the_step_by_step_loop():
+    # fx_model_train, gathering each mini-batch through the epoch's order,
+    # gives the same parameters bit for bit as gathering the rows first and
+    # calling fx_model_train_step per mini-batch (ragged last batch included)
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(11)
+    n, batch, epochs, lr = 300, 64, 3, 2e-3
+    X, y = _data(rng, n)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    perm = np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+    a, p, mean, std = _model(fx, np.random.default_rng(12))
+    b = fx.Model(F, H, HEADS)
+    b.set(p, mean, std)
+    loss = torch.zeros(1, device="cuda")
+    last = []
+    for e in range(epochs):
+        idx = torch.from_numpy(perm[e].astype(np.int64)).cuda()
+        Xp, yp = Xd[idx].contiguous(), yd[idx].contiguous()
+        for s in range(0, n, batch):
+            a.train_step(Xp[s:s + batch], yp[s:s + batch], lr, loss)
+        last.append(loss.clone())
+    losses = torch.zeros(epochs, device="cuda")
+    b.train(Xd, yd, epochs, batch, lr, perm, losses)
+    torch.cuda.synchronize()
+    pa, pb = a.get()[0], b.get()[0]
+    assert not np.array_equal(pa, p)
+    assert np.array_equal(pa, pb)
+    assert torch.cat(last).cpu().tolist() == losses.cpu().tolist()
+    # natural order: the same as perm = arange each epoch
+    c = fx.Model(F, H, HEADS)
+    c.set(p, mean, std)
+    d = fx.Model(F, H, HEADS)
+    d.set(p, mean, std)
+    c.train(Xd, yd, 2, batch, lr)
+    d.train(Xd, yd, 2, batch, lr, np.tile(np.arange(n, dtype=np.int32), (2, 1)))
+    torch.cuda.synchronize()
+    assert np.array_equal(c.get()[0], d.get()[0])
+
+
+def test_native_training_rejects_a_bad_order():
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(13)
+    X, y = _data(rng, 10)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    m, p, _, _ = _model(fx, rng)
+    bad = np.tile(np.arange(10, dtype=np.int32), (2, 1))
+    bad[1, 3] = 4  # a repeated row
+    with pytest.raises(fx.FxError):
+        m.train(Xd, yd, 2, 4, 1e-3, bad)
+    bad[1, 3] = 10  # out of range
+    with pytest.raises(fx.FxError):
+        m.train(Xd, yd, 2, 4, 1e-3, bad)
+    assert np.array_equal(m.get()[0], p)  # nothing ran
