@@ -48,5 +48,6 @@ def test_choice_for_the_matrix_workload():
     import paper_2604_22242_amd as fx
     info = fx.Tape(model.C2_NODES).info()
     ch = choose(tune.features(info, "f32", (8192, 8192), None))
-    # the evaluation report's pick for the fused Z: 128 threads, EPT 1, 16 B
-    assert model.config_of(ch, None, "f32") == (128, 1, 16, 0)
+    # the evaluation report's pick for the fused Z: 128 threads, EPT 1, 16 B,
+    # 32 blocks per CU
+    assert model.config_of(ch, None, "f32") == (128, 1, 16, 32 * 256)
