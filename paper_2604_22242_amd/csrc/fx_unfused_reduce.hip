@@ -1,7 +1,7 @@
 // Unfused baseline, reductions and whole expressions: reductions of
 // materialised arrays, and each workload expression evaluated one operator
 // at a time through caller-provided temporaries.
-#include "fx_kernels.hpp"
+#include "fx.hpp"
 
 using namespace fx;
 
@@ -36,25 +36,23 @@ int fx_reduce(int kind, fx_dtype dt, const void* A, const void* B, fx_shape s, v
   if (int rc = check_shape(s)) return rc;
   if (dt == FX_U32) {
     auto a = leaf<uint32_t>(A, s.n_rows, s.n_cols);
-    if (kind == FX_R_ACCU) return reduce_full<map_id>(a, out, ws, ws_bytes, cfg, S(stream));
-    if (kind == FX_R_DOT) {
-      auto b = leaf<uint32_t>(B, s.n_rows, s.n_cols);
-      return reduce_full<map_id>(a % b, out, ws, ws_bytes, cfg, S(stream));
-    }
+    uint64_t* o = static_cast<uint64_t*>(out);
+    if (kind == FX_R_ACCU) return accu(a, o, ws, ws_bytes, cfg, S(stream));
+    if (kind == FX_R_DOT)
+      return dot(a, leaf<uint32_t>(B, s.n_rows, s.n_cols), o, ws, ws_bytes, cfg, S(stream));
     return fail(FX_E_DTYPE, "reduction %d not defined for u32", kind);
   }
   return with_fp(dt, [&](auto t) {
     using T = typename decltype(t)::type;
     auto a = leaf<T>(A, s.n_rows, s.n_cols);
+    double* o = static_cast<double*>(out);
     switch (kind) {
-      case FX_R_ACCU: return reduce_full<map_id>(a, out, ws, ws_bytes, cfg, S(stream));
-      case FX_R_NORM: return reduce_full<map_sq>(a, out, ws, ws_bytes, cfg, S(stream));
-      case FX_R_DOT: {
-        auto b = leaf<T>(B, s.n_rows, s.n_cols);
-        return reduce_full<map_id>(a % b, out, ws, ws_bytes, cfg, S(stream));
-      }
+      case FX_R_ACCU: return accu(a, o, ws, ws_bytes, cfg, S(stream));
+      case FX_R_NORM: return norm_fro(a, o, ws, ws_bytes, cfg, S(stream));
+      case FX_R_DOT: return dot(a, leaf<T>(B, s.n_rows, s.n_cols), o, ws, ws_bytes, cfg, S(stream));
       case FX_R_COLSUM: case FX_R_ROWSUM:
-        return reduce_dim(kind, a, static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, S(stream));
+        return sum(a, kind == FX_R_COLSUM ? 0 : 1, static_cast<acc_out_t<T>*>(out), ws, ws_bytes,
+                   cfg, S(stream));
     }
     return fail(FX_E_ARG, "unknown reduction kind %d", kind);
   });
