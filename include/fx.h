@@ -357,7 +357,8 @@ int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* 
  * column sums 256 threads, EPT 2 (1 for half types), one block per column
  * when there are at least as many columns as CUs; row sums 256 threads,
  * EPT 2, one row per thread, 64 column chunks.  The split default applies
- * only when all of cfg is 0 (or cfg is NULL). */
+ * only when all of cfg is 0 (or cfg is NULL); then a model attached with
+ * fx_tape_set_model chooses instead. */
 int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);
@@ -462,7 +463,8 @@ void fx_batch_destroy(fx_batch* b);
 /* Time tape t, run exactly as fx_tape_eval(t, dt, inputs, n_inputs, shape,
  * kind, out, ws, ...) would run it, under each of cfgs[0..n_cfgs): `warmup`
  * untimed launches, then `reps` launches each bracketed by HIP events on
- * `stream`.  ms[c*reps + r] receives the times in milliseconds; a
+ * `stream` (an all-zero configuration is the library defaults, even with a
+ * model attached to t).  ms[c*reps + r] receives the times in milliseconds; a
  * configuration that is not compiled or does not fit (FX_E_UNSUPPORTED,
  * FX_E_CONFIG, FX_E_WORKSPACE) gets NaN and the sweep goes on.  ws must hold
  * the largest workspace among the configurations.  Synchronous. */
@@ -584,6 +586,15 @@ int fx_model_load(const char* path, fx_model** out);
  * autotuner's grid for `kind` and dt (fx_tune_grid), on the host. */
 int fx_model_predict(const fx_model* m, const float* features, int kind, fx_dtype dt,
                      fx_launch* out);
+
+/* Attach model m to tape t (NULL detaches).  From then on, fx_tape_eval
+ * calls on t that leave the launch configuration to the library (cfg NULL
+ * or all zero) run the model's pick for their dtype, shape and kind
+ * (fx_tape_features, then fx_model_predict, on the host; the last pick is
+ * cached in the tape).  A pick whose workspace exceeds the call's ws_bytes
+ * falls back to the defaults.  Explicit configurations, fx_tune_time and
+ * fx_autotune are unaffected.  m must stay alive while attached. */
+int fx_tape_set_model(fx_tape* t, const fx_model* m);
 
 /* ---- measurement kernels ------------------------------------------------- */
 

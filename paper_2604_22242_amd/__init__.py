@@ -151,6 +151,7 @@ _SIGS = {
     "fx_tape_features": (ctypes.c_int32, [_P, _I, Shape, _I, ctypes.POINTER(ctypes.c_float),
                                           ctypes.c_int32]),
     "fx_model_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "fx_tape_set_model": (_I, [_P, _P]),
     "fx_model_predict": (_I, [_P, ctypes.POINTER(ctypes.c_float), _I, _I, _LP]),
     "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
     "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
@@ -448,6 +449,17 @@ class Tape:
 
     def program(self):
         return fx_tape_program(self)
+
+    def set_model(self, model):
+        """fx_tape_set_model: evaluations that leave the launch configuration
+        to the library take `model`'s pick (None detaches).  The tape keeps a
+        reference, so the model outlives the attachment."""
+        check(lib().fx_tape_set_model(self.handle, model.handle if model is not None else None))
+        self._model = model
+
+
+def fx_tape_set_model(tape: Tape, model):
+    tape.set_model(model)
 
 
 def fx_tape_create(nodes) -> Tape:

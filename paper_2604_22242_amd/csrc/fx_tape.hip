@@ -294,6 +294,27 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
 
 using namespace fx;
 
+namespace fx {
+
+int tape_eval_exact(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                    fx_shape s, int kind, void* out, void* ws, size_t ws_bytes,
+                    const fx_launch* cfg, hipStream_t st) {
+  if (!t) return fail(FX_E_ARG, "NULL tape");
+  if (int rc = check_shape(s)) return rc;
+  if (n_inputs < t->prog.n_in || (t->prog.n_in > 0 && !inputs))
+    return fail(FX_E_ARG, "tape reads %d inputs, %d given", t->prog.n_in, n_inputs);
+  switch (dt) {
+    case FX_F32: return tape_eval_typed<float>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);
+    case FX_F64: return tape_eval_typed<double>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);
+    case FX_BF16: return tape_eval_typed<bf16_t>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);
+    case FX_F16: return tape_eval_typed<f16_t>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);
+    default: break;
+  }
+  return fail(FX_E_DTYPE, "tapes evaluate floating-point dtypes only");
+}
+
+}  // namespace fx
+
 extern "C" {
 
 int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out) {
@@ -332,21 +353,43 @@ int fx_tape_describe(const fx_tape* t, fx_tape_info* out) {
   return FX_OK;
 }
 
+int fx_tape_set_model(fx_tape* t, const fx_model* m) {
+  if (!t) return fail(FX_E_ARG, "NULL tape");
+  std::lock_guard<std::mutex> g(t->mu);
+  t->model = m;
+  t->have_choice = false;
+  return FX_OK;
+}
+
 int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                  fx_shape s, int kind, void* out, void* ws, size_t ws_bytes, const fx_launch* cfg,
                  void* stream) {
   if (!t) return fail(FX_E_ARG, "NULL tape");
+  const bool library_choice =
+      !cfg || (!cfg->block && !cfg->ept && !cfg->vec_bytes && !cfg->split);
+  if (!library_choice || !t->model)
+    return tape_eval_exact(t, dt, inputs, n_inputs, s, kind, out, ws, ws_bytes, cfg, S(stream));
   if (int rc = check_shape(s)) return rc;
-  if (n_inputs < t->prog.n_in || (t->prog.n_in > 0 && !inputs))
-    return fail(FX_E_ARG, "tape reads %d inputs, %d given", t->prog.n_in, n_inputs);
-  switch (dt) {
-    case FX_F32: return tape_eval_typed<float>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, S(stream));
-    case FX_F64: return tape_eval_typed<double>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, S(stream));
-    case FX_BF16: return tape_eval_typed<bf16_t>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, S(stream));
-    case FX_F16: return tape_eval_typed<f16_t>(t->prog, inputs, s, kind, out, ws, ws_bytes, cfg, S(stream));
-    default: break;
+  fx_launch pick;
+  {
+    std::lock_guard<std::mutex> g(t->mu);
+    if (!(t->have_choice && t->choice_dt == dt && t->choice_kind == kind &&
+          t->choice_shape.n_rows == s.n_rows && t->choice_shape.n_cols == s.n_cols)) {
+      float f[32];
+      const int32_t nf = fx_tape_features(t, dt, s, kind, f, 32);
+      if (nf < 0) return -nf;
+      if (int rc = fx_model_predict(t->model, f, kind, dt, &t->choice)) return rc;
+      t->have_choice = true;
+      t->choice_dt = dt;
+      t->choice_kind = kind;
+      t->choice_shape = s;
+    }
+    pick = t->choice;
   }
-  return fail(FX_E_DTYPE, "tapes evaluate floating-point dtypes only");
+  // a choice whose workspace the caller did not provide falls back to the
+  // defaults (whose workspace fx_workspace_bytes covers)
+  if (kind != 0 && fx_workspace_bytes(kind, dt, s, &pick) > ws_bytes) pick = fx_launch{0, 0, 0, 0};
+  return tape_eval_exact(t, dt, inputs, n_inputs, s, kind, out, ws, ws_bytes, &pick, S(stream));
 }
 
 }  // extern "C"

@@ -21,6 +21,7 @@
 // interpreting them one vector at a time.
 #pragma once
 
+#include <mutex>
 #include "fx_kernels.hpp"
 
 namespace fx {
@@ -336,8 +337,25 @@ int tape_compile(const fx_node* nodes, int32_t n_nodes, tape_prog* prog, fx_tape
 
 }  // namespace fx
 
-// The opaque handle of the C ABI.
+// The opaque handle of the C ABI.  With a model attached, evaluations that
+// leave the launch configuration to the library take the model's choice;
+// the last choice is cached (one key: dtype, shape, kind) under `mu`.
 struct fx_tape {
   fx::tape_prog prog;
   fx_tape_info info;
+  const fx_model* model = nullptr;
+  mutable std::mutex mu;
+  mutable bool have_choice = false;
+  mutable fx_dtype choice_dt = FX_F32;
+  mutable fx_shape choice_shape{0, 0};
+  mutable int choice_kind = 0;
+  mutable fx_launch choice{0, 0, 0, 0};
 };
+
+namespace fx {
+// fx_tape_eval without the model: `cfg` as given (fx_tune_time times the
+// all-default configuration as the library's defaults).
+int tape_eval_exact(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                    fx_shape s, int kind, void* out, void* ws, size_t ws_bytes,
+                    const fx_launch* cfg, hipStream_t st);
+}  // namespace fx

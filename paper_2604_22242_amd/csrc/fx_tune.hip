@@ -18,9 +18,6 @@ extern "C" int fx_model_create(int32_t n_features, int32_t hidden, const int32_t
 extern "C" int fx_model_set(fx_model* m, const float* params, const float* mean, const float* stdv);
 extern "C" int fx_model_choose(const fx_model* m, const float* features, int32_t* choice);
 extern "C" void fx_model_destroy(fx_model* m);
-extern "C" int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs,
-                            int32_t n_inputs, fx_shape s, int kind, void* out, void* ws,
-                            size_t ws_bytes, const fx_launch* cfg, void* stream);
 
 extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* inputs,
                             int32_t n_inputs, fx_shape shape, int kind, void* out, void* ws,
@@ -39,7 +36,7 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
   for (int c = 0; c < n_cfgs && status == FX_OK; ++c) {
     float* row = ms + (size_t)c * reps;
     auto run = [&]() {
-      return fx_tape_eval(t, dt, inputs, n_inputs, shape, kind, out, ws, ws_bytes, &cfgs[c], stream);
+      return tape_eval_exact(t, dt, inputs, n_inputs, shape, kind, out, ws, ws_bytes, &cfgs[c], st);
     };
     int rc = run();  // the first launch also validates the configuration
     if (rc == FX_E_UNSUPPORTED || rc == FX_E_CONFIG || rc == FX_E_WORKSPACE) {

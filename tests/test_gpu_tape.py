@@ -182,3 +182,55 @@ def test_native_autotune(kind, tmp_path):
     v, mu = oracle.evaluate(oracle_expr(C2_NODES), host, "f32", shape=shape,
                             reduce=None if kind == 0 else "colsum")
     assert_close(from_dev(out, "f32"), v, mu, "f32", "autotuned %s" % (best,))
+
+
+@pytest.mark.parametrize("red", [None, "accu", "colsum", "rowsum", "norm"])
+def test_attached_model_chooses_the_launch(red):
+    # a tape with the shipped model attached runs, where the caller leaves the
+    # launch to the library, exactly the model's pick for each shape (bit for
+    # bit the same result as passing that pick), falls back to the defaults
+    # when the caller's workspace only covers those, and matches the oracle
+    torch, fx = need_gpu()
+    import os
+    kind = {None: 0, "accu": fx.R_ACCU, "colsum": fx.R_COLSUM, "rowsum": fx.R_ROWSUM,
+            "norm": fx.R_NORM}[red]
+    nodes, k, _ = trees.random_tree(5, 17, depth=(4, 7))
+    model = fx.fx_model_load(os.path.join(os.path.dirname(fx.LIB_PATH), "launch_model.fxm"))
+    attached, plain = fx.Tape(nodes), fx.Tape(nodes)
+    attached.set_model(model)
+    od = "f32" if kind in (0, fx.R_COLSUM, fx.R_ROWSUM) else "f64"
+    for shape in [(3000, 257), (1000, 99)]:  # a new shape replaces the cached pick
+        n = shape[0] * shape[1]
+        host, dev = tree_inputs(5, 17, k, n, "f32")
+
+        def out_buf():
+            if kind in (fx.R_ACCU, fx.R_NORM):
+                return torch.zeros(1, dtype=torch.float64, device="cuda")
+            return empty({0: n, fx.R_COLSUM: shape[1], fx.R_ROWSUM: shape[0]}[kind], "f32")
+
+        pick = model.predict(fx.fx_tape_features(plain, fx.F32, shape, kind), kind, fx.F32)
+        ws_pick = fx.workspace(kind, fx.F32, shape, pick) if kind else None
+        a, b = out_buf(), out_buf()
+        fx.fx_tape_eval(attached, dev, a, shape, kind, ws_pick)
+        fx.fx_tape_eval(plain, dev, b, shape, kind, ws_pick, cfg=pick)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (shape, pick)
+        v, mu = oracle.evaluate(oracle_expr(nodes), host, "f32", shape=shape, reduce=red)
+        assert_close(from_dev(a, od), v, mu, "f32", "model pick %s %s" % (pick, shape))
+        if kind:
+            need_pick = fx.fx_workspace_bytes(kind, fx.F32, shape, pick)
+            need_def = fx.fx_workspace_bytes(kind, fx.F32, shape, None)
+            ws_def = fx.workspace(kind, fx.F32, shape, None)
+            c, d = out_buf(), out_buf()
+            fx.fx_tape_eval(attached, dev, c, shape, kind, ws_def)
+            fx.fx_tape_eval(plain, dev, d, shape, kind, ws_def,
+                            cfg=pick if need_pick <= need_def else None)
+            torch.cuda.synchronize()
+            assert torch.equal(c, d), (shape, pick, need_pick, need_def)
+    attached.set_model(None)  # detached: the defaults again
+    a, b = out_buf(), out_buf()
+    ws_def = fx.workspace(kind, fx.F32, shape, None) if kind else None
+    fx.fx_tape_eval(attached, dev, a, shape, kind, ws_def)
+    fx.fx_tape_eval(plain, dev, b, shape, kind, ws_def)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
