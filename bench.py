@@ -306,10 +306,11 @@ def paper_suite_detail(fx, torch, stream, reps):
 
 def modes_detail(fx, torch, stream, reps):
     """One expression three ways: compile-time template (the fused kernel),
-    run-time tape (interpreter) and run-time source (hipRTC-compiled at first
-    use).  The matrix workload's Z and its column sums over 2^26 FP32
-    elements, and the deepest of the first 200 generated tuning trees
-    (depth <= 8) over 2^26 elements."""
+    run-time tape (interpreter; also with the shipped launch model attached)
+    and run-time source (hipRTC-compiled at first use).  The matrix
+    workload's Z and its column sums over 2^26 FP32 elements, and the
+    deepest of the first 200 generated tuning trees (depth <= 8) over 2^26
+    elements."""
     import synth
     from synth import trees
     from paper_2604_22242_amd.model import C2_NODES
@@ -317,6 +318,17 @@ def modes_detail(fx, torch, stream, reps):
     ins = [torch.from_numpy(synth.fill(2, t, n, "f32")).cuda() for t in range(4)]
     Z = torch.empty(n, device="cuda")
     out = {}
+    model = fx.fx_model_load(os.path.join(ROOT, "paper_2604_22242_amd", "launch_model.fxm"))
+
+    def with_model(nodes, inputs, o, shape, kind=0):
+        t = fx.Tape(nodes)
+        t.set_model(model)
+        pick = model.predict(fx.fx_tape_features(t, fx.F32, shape, kind), kind, fx.F32)
+        w = fx.workspace(kind, fx.F32, shape, pick) if kind else None
+        ms = event_ms(torch, stream, lambda: fx.fx_tape_eval(t, inputs, o, shape, kind, w,
+                                                             stream=stream), reps)
+        return {"tape_model_ms": round(ms, 4), "model_pick": list(pick)}
+
     r = fx.Rtc(C2_NODES, fx.F32)
     tape = fx.Tape(C2_NODES)
     out["c2_z"] = {
@@ -324,6 +336,7 @@ def modes_detail(fx, torch, stream, reps):
             *ins[:3], Z, (ROWS, COLS), stream=stream), reps), 4),
         "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
             tape, ins[:3], Z, (n, 1), stream=stream), reps), 4),
+        **with_model(C2_NODES, ins[:3], Z, (n, 1)),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:3], Z, stream=stream), reps), 4),
         "hiprtc_compile_ms": round(r.compile_ms(), 1)}
@@ -337,6 +350,7 @@ def modes_detail(fx, torch, stream, reps):
             *ins[:3], cs, shape, ws, stream=stream), reps), 4),
         "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
             tape, ins[:3], cs, shape, fx.R_COLSUM, ws, stream=stream), reps), 4),
+        **with_model(C2_NODES, ins[:3], cs, shape, fx.R_COLSUM),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:3], cs, shape, ws, stream=stream), reps), 4),
         "hiprtc_compile_ms": round(r.compile_ms(), 1)}
@@ -350,6 +364,7 @@ def modes_detail(fx, torch, stream, reps):
         "tape_instructions": tape.info()["n_instructions"],
         "tape_ms": round(event_ms(torch, stream, lambda: fx.fx_tape_eval(
             tape, ins[:k], Z, (n, 1), stream=stream), reps), 4),
+        **with_model(best["nodes"], ins[:k], Z, (n, 1)),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:k], Z, stream=stream), reps), 4),
         "hiprtc_compile_ms": round(r.compile_ms(), 1)}
