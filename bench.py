@@ -471,10 +471,12 @@ def main():
                     help="fused FP32 steps, then the same steps with BF16 and FP64 storage, "
                          "plus one 1 GiB copy (the known-size kernel that scales hardware "
                          "byte counters); no CPU baseline")
-    ap.add_argument("--profile-set", choices=("step", "views", "paper", "batch"), default="step",
+    ap.add_argument("--profile-set", choices=("step", "views", "paper", "batch", "precision", "c1"),
+                    default="step",
                     help="with --profile: which kernels to run (the matrix-workload step, the "
-                         "paper's strided-view expressions, the paper's expression suite, or the "
-                         "4096-expression batch), always followed by the 1 GiB copy")
+                         "paper's strided-view expressions, the paper's expression suite, the "
+                         "4096-expression batch, the 2^28 half-storage workload, or the 2^20 "
+                         "vector workload with its u32 form), always followed by the 1 GiB copy")
     a = ap.parse_args()
     if a.profile:
         a.no_extra = a.no_cpu = True
@@ -490,7 +492,8 @@ def main():
     stream = torch.cuda.current_stream()
     if a.profile and a.profile_set != "step":
         run = {"views": paper_views_detail, "paper": paper_suite_detail,
-               "batch": batch_detail}[a.profile_set]
+               "batch": batch_detail, "precision": precision_detail,
+               "c1": c1_detail}[a.profile_set]
         log("bench: profile set %s, %d repetitions" % (a.profile_set, a.steps))
         res = run(fx, torch, stream, a.steps)
         torch.cuda.empty_cache()
