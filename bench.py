@@ -145,6 +145,22 @@ def copy_ceiling(fx, torch, stream, nbytes=1 << 31, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def cold_ms(torch, stream, fn, reps, flush):
+    """Median HIP-event time of fn() with `flush` overwritten before each
+    launch (outside the events): no input left in the 256 MB last-level
+    cache."""
+    times = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return sorted(times)[len(times) // 2]
+
+
 def event_ms(torch, stream, fn, reps):
     """Mean HIP-event time of fn() over reps launches after two warm-ups."""
     for _ in range(2):
@@ -515,6 +531,20 @@ def main():
     detail = {"fp32_fused": per}
     dominant_bytes = wl.bytes[dominant]
     achieved = dominant_bytes / (dms_live[dominant] * 1e-3) / 1e9
+    # the same kernels with a 512 MB write before each launch: the 1 GiB
+    # working set of a warm step keeps part of itself in the last-level cache
+    # (not in profile runs, whose per-kernel averages must be the steps')
+    achieved_cold = None
+    if not a.profile:
+        flush = torch.empty(128 << 20, device="cuda")
+        with torch.cuda.stream(stream):
+            cold = {r: cold_ms(torch, stream, lambda: wl.fused(r, stream), 11, flush)
+                    for r in RESULTS}
+        del flush
+        for r in RESULTS:
+            per[r]["cold_ms"] = round(cold[r], 5)
+            per[r]["cold_GB/s"] = round(wl.bytes[r] / (cold[r] * 1e-3) / 1e9, 1)
+        achieved_cold = round(dominant_bytes / (cold[dominant] * 1e-3) / 1e9, 1)
 
     if not a.no_extra:
         log("bench: unfused FP32 baseline")
@@ -607,7 +637,9 @@ def main():
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic() if dominant == "z" else None,
-                     "algorithmic_bytes": dominant_bytes},
+                     "algorithmic_bytes": dominant_bytes,
+                     "achieved_cold": achieved_cold,
+                     "frac_cold": round(achieved_cold / PEAK_HBM_GBS, 4) if achieved_cold else None},
         "cpu_baseline": cpu,
         "detail": detail,
     }
