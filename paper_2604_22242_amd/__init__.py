@@ -661,7 +661,7 @@ def fx_tape_features(tape: Tape, dt, shape, kind=0) -> list:
     out = (ctypes.c_float * 25)()
     n = lib().fx_tape_features(tape.handle, dt, _shape(shape), kind, out, 25)
     if n < 0:
-        check(n)
+        check(-n)
     return [out[i] for i in range(n)]
 
 
@@ -669,9 +669,9 @@ def fx_tune_grid(kind, dt) -> list:
     """The autotuner's configuration grid (65 tuples, the default last)."""
     n = lib().fx_tune_grid(kind, dt, None, 0)
     if n < 0:
-        check(n)
+        check(-n)
     arr = (Launch * n)()
-    check(min(0, lib().fx_tune_grid(kind, dt, arr, n)))
+    check(-min(0, lib().fx_tune_grid(kind, dt, arr, n)))
     return [arr[i].as_tuple() for i in range(n)]
 
 

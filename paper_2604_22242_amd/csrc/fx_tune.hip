@@ -104,8 +104,8 @@ float median_of(float* v, int n) {
 
 extern "C" int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t cap) {
   const int elem = elem_of(dt);
-  if (!elem) return fail(FX_E_DTYPE, "tapes take floating-point dtypes");
-  if (kind < 0 || kind > FX_R_NORM) return fail(FX_E_ARG, "unknown kind %d", kind);
+  if (!elem) return -fail(FX_E_DTYPE, "tapes take floating-point dtypes");
+  if (kind < 0 || kind > FX_R_NORM) return -fail(FX_E_ARG, "unknown kind %d", kind);
   if (!out || cap < kGridSize) return kGridSize;
   int sp[4];
   grid_splits(kind, device_cus(), sp);
@@ -201,7 +201,7 @@ extern "C" int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inp
   const auto t0 = std::chrono::steady_clock::now();
   fx_launch grid[kGridSize];
   const int32_t n = fx_tune_grid(kind, dt, grid, kGridSize);
-  if (n < 0) return n;
+  if (n < 0) return -n;
   std::vector<float> ms((size_t)n * reps), med(n);
   if (int rc = fx_tune_time(t, dt, inputs, n_inputs, shape, kind, out, ws, ws_bytes, grid, n,
                             warmup, reps, ms.data(), stream))
@@ -239,11 +239,12 @@ constexpr int kModelFeatures = 25;
 
 extern "C" int32_t fx_tape_features(const fx_tape* t, fx_dtype dt, fx_shape shape, int kind,
                                     float* out, int32_t cap) {
-  if (!t) return fail(FX_E_ARG, "NULL tape");
+  if (!t) return -fail(FX_E_ARG, "NULL tape");
   const int elem = elem_of(dt);
-  if (!elem) return fail(FX_E_DTYPE, "tapes take floating-point dtypes");
-  if (kind < 0 || kind > FX_R_NORM || kind == FX_R_DOT) return fail(FX_E_ARG, "unknown kind %d", kind);
-  if (shape.n_rows < 0 || shape.n_cols < 0) return fail(FX_E_ARG, "negative shape");
+  if (!elem) return -fail(FX_E_DTYPE, "tapes take floating-point dtypes");
+  if (kind < 0 || kind > FX_R_NORM || kind == FX_R_DOT)
+    return -fail(FX_E_ARG, "unknown kind %d", kind);
+  if (shape.n_rows < 0 || shape.n_cols < 0) return -fail(FX_E_ARG, "negative shape");
   if (!out || cap < kModelFeatures) return kModelFeatures;
   const fx_tape_info& I = t->info;
   const double rows = (double)shape.n_rows, cols = (double)shape.n_cols;

@@ -1,6 +1,8 @@
 """CPU tests of the autotuner's configuration grid and model features."""
 import math
 
+import pytest
+
 from synth import trees
 
 
@@ -115,3 +117,24 @@ def test_model_file_layout(tmp_path):
         meta["n_features"], meta["hidden"], meta["heads"])
     params = np.fromfile(base + ".bin", np.float32)
     assert c.endswith(params.tobytes())
+
+
+def test_count_returning_calls_report_errors_as_negative_status():
+    # fx_tune_grid and fx_tape_features return a count, so their errors are
+    # negative fx_status values (never a count the caller could use)
+    import paper_2604_22242_amd as fx
+    L = fx.lib()
+    assert L.fx_tune_grid(0, fx.U32, None, 0) == -3        # FX_E_DTYPE
+    assert L.fx_tune_grid(99, fx.F32, None, 0) == -1       # FX_E_ARG
+    assert L.fx_tune_grid(0, fx.F32, None, 0) == 65
+    tape = fx.Tape([("leaf", -1, -1, 0, 0.0), ("exp", 0, -1, -1, 0.0)])
+    shape = fx.Shape(100, 1)
+    assert L.fx_tape_features(tape.handle, fx.U32, shape, 0, None, 0) == -3
+    assert L.fx_tape_features(None, fx.F32, shape, 0, None, 0) == -1
+    assert L.fx_tape_features(tape.handle, fx.F32, shape, fx.R_DOT, None, 0) == -1
+    assert L.fx_tape_features(tape.handle, fx.F32, shape, 0, None, 0) == 25
+    for call in (lambda: fx.fx_tune_grid(0, fx.U32),
+                 lambda: fx.fx_tape_features(tape, fx.U32, (100, 1), 0)):
+        with pytest.raises(fx.FxError) as ei:
+            call()
+        assert ei.value.code == 3
