@@ -197,6 +197,60 @@ def et_check(m: Model, cus: int, rows=8192, cols=8192, reps=5):
     return out
 
 
+def attached_check(path, start, count, warmup=2, reps=5):
+    """End to end: held-out tuning items (seed 6) evaluated by fx_tape_eval
+    with the model file at `path` attached to the tape, and without it (the
+    interpreter defaults); each the median of `reps` event-timed launches
+    after `warmup`.  Returns the geometric-mean speedup and per-kind ones."""
+    import statistics
+    import torch
+    from synth import trees
+    from . import Tape, fx_model_load, fx_tape_eval
+    from .tune import DTYPE, KIND, Pool
+    model = fx_model_load(path)
+    pool = Pool()
+    stream = torch.cuda.current_stream()
+
+    def timed(tape, ins, shape, kind, dt):
+        run = lambda: fx_tape_eval(tape, ins, pool.out, shape, kind, pool.ws if kind else None,
+                                   dt=dt, stream=stream)
+        for _ in range(warmup):
+            run()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return statistics.median(ts)
+
+    ratios, by_kind = [], {}
+    for i in range(start, start + count):
+        it = trees.tuning_item(6, i)
+        kind, dt = KIND[it["reduce"]], DTYPE[it["dtype"]]
+        n = it["shape"][0] * it["shape"][1]
+        ins = pool.views(it["dtype"], n, it["n_inputs"])
+        plain, attached = Tape(it["nodes"]), Tape(it["nodes"])
+        attached.set_model(model)
+        if i % 2:  # alternate which runs first
+            ta = timed(attached, ins, it["shape"], kind, dt)
+            tp = timed(plain, ins, it["shape"], kind, dt)
+        else:
+            tp = timed(plain, ins, it["shape"], kind, dt)
+            ta = timed(attached, ins, it["shape"], kind, dt)
+        r = tp / ta
+        ratios.append(r)
+        by_kind.setdefault("%s/%s" % (it["reduce"], it["dtype"]), []).append(r)
+    gm = lambda v: math.exp(sum(math.log(x) for x in v) / len(v))
+    return {"items": len(ratios), "speedup_geomean": round(gm(ratios), 4),
+            "faster_by_5pct": round(sum(r > 1.05 for r in ratios) / len(ratios), 4),
+            "slower_by_5pct": round(sum(r < 1 / 1.05 for r in ratios) / len(ratios), 4),
+            "by_kind": {k: {"items": len(v), "speedup_geomean": round(gm(v), 4)}
+                        for k, v in sorted(by_kind.items())}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", nargs="+", default=[])
@@ -206,6 +260,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--attached", type=int, nargs=2, metavar=("START", "COUNT"), default=None,
+                    help="with --model: time held-out items through tapes with the model "
+                         "attached against the interpreter defaults")
     ap.add_argument("--et-check", action="store_true",
                     help="also apply the model to the compile-time matrix-workload kernels")
     a = ap.parse_args(argv)
@@ -227,6 +284,10 @@ def main(argv=None):
         rep["heldout"] = evaluate(m, ho, cus)
     if a.et_check:
         rep["compile_time_kernels"] = et_check(m, cus)
+    if a.attached:
+        if not a.model:
+            ap.error("--attached needs --model")
+        rep["attached"] = attached_check(a.model + ".fxm", *a.attached)
     if a.out:
         save(m, a.out)
     print(json.dumps(rep, indent=1), flush=True)
