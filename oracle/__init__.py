@@ -34,15 +34,38 @@ U_HALF = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
 HALF_SUBNORMAL_HALF_SPACING = {"bf16": 2.0 ** -134, "f16": 2.0 ** -25}
 F16_OVERFLOW = 65520.0   # nearest-even rounding of |z| >= 65520 to FP16 gives inf
 
+# Allowances of the device elementary functions in the running error bound,
+# in units of the compute type's roundoff relative to the result (2 = one
+# ulp at most), per compute type.  Each must be at least the largest relative
+# error that the sweep of the device functions against libm finds over the
+# function's domain of use (every FP32 input; a sample of FP64 inputs).
+F_ALLOW = {
+    "f32": {"exp": 2.0, "log": 2.0, "tanh": 2.0, "pow": 2.0},
+    "f64": {"exp": 2.0, "log": 2.0, "tanh": 2.0, "pow": 2.0},
+}
+F_ORDER = ("exp", "log", "tanh", "pow")
+
 
 def build(force: bool = False) -> str:
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "mathref.c")]
+    newest = max(os.path.getmtime(f) for f in srcs)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _SO)
     return _SO
+
+
+class SweepStats(ctypes.Structure):
+    """Result of a sweep of a device elementary function (mathref.c)."""
+    _fields_ = [("max_rel_u", ctypes.c_double), ("max_ulp", ctypes.c_double),
+                ("argmax", ctypes.c_int64), ("first_bad", ctypes.c_int64),
+                ("n_bad", ctypes.c_int64), ("n_subnormal", ctypes.c_int64),
+                ("max_sub_ulp", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -58,19 +81,54 @@ def lib():
         L.or_eval.restype = ctypes.c_int
         L.or_eval.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, P,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                              ctypes.c_double, ctypes.c_double, P, P]
+                              ctypes.c_double, P, P, P]
         L.or_eval_views.restype = ctypes.c_int
         L.or_eval_views.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, P,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                                    ctypes.c_double, ctypes.c_double, P, P, P, P, P]
+                                    ctypes.c_double, P, P, P, P, P, P]
         L.or_eval_u32.restype = ctypes.c_int
         L.or_eval_u32.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, P,
                                   ctypes.c_int64, P, P]
+        L.mr_sweep_f32.restype = ctypes.c_int
+        L.mr_sweep_f32.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double,
+                                   P, ctypes.c_double, ctypes.POINTER(SweepStats)]
+        L.mr_sweep_f64.restype = ctypes.c_int
+        L.mr_sweep_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P,
+                                   ctypes.c_double, ctypes.POINTER(SweepStats)]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_threads.restype = None
         L.or_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
+
+
+MATH_FN = {"exp": 0, "log": 1, "tanh": 2, "sqrt": 3, "pow": 4}
+
+
+def sweep_f32(fn: str, bits0: int, got, f_allow: float, k: float = 0.0) -> dict:
+    """Errors of device FP32 results `got` (float32 array) for the inputs
+    whose bit patterns are bits0, bits0 + 1, ...: the largest error relative
+    to the libm value in units of 2^-24 (max_rel_u), in ulps (max_ulp), and
+    the first index beyond `f_allow` (first_bad, -1 if none)."""
+    got = np.ascontiguousarray(got, np.float32)
+    st = SweepStats()
+    if lib().mr_sweep_f32(MATH_FN[fn], int(bits0), got.size, float(k), got.ctypes.data,
+                          float(f_allow), ctypes.byref(st)) != 0:
+        raise ValueError("bad sweep arguments")
+    return st.as_dict()
+
+
+def sweep_f64(fn: str, x, got, f_allow: float, k: float = 0.0) -> dict:
+    """As sweep_f32 for FP64 results `got` at the inputs `x`, referenced to
+    extended precision; errors in units of 2^-53."""
+    x = np.ascontiguousarray(x, np.float64)
+    got = np.ascontiguousarray(got, np.float64)
+    assert x.size == got.size
+    st = SweepStats()
+    if lib().mr_sweep_f64(MATH_FN[fn], x.ctypes.data, x.size, float(k), got.ctypes.data,
+                          float(f_allow), ctypes.byref(st)) != 0:
+        raise ValueError("bad sweep arguments")
+    return st.as_dict()
 
 
 def num_threads() -> int:
@@ -297,13 +355,14 @@ def compute_unit(dtype: str) -> float:
 
 
 def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
-             fexp: float = 2.0, input_dtypes=None):
+             f_allow=None, input_dtypes=None):
     """Evaluate `expr` over stored inputs (numpy arrays of the storage dtype,
     bf16 as uint16 bit patterns).  shape=(n_rows, n_cols), column-major;
     default (n, 1).  input_dtypes: per-input storage dtypes when they differ
-    from `dtype` (mixed-dtype leaves).  Returns (value, mu): arrays of FP64
-    values and running error bounds in units of u_c (default: the compute
-    type's roundoff)."""
+    from `dtype` (mixed-dtype leaves).  f_allow: the elementary functions'
+    allowances {exp, log, tanh, pow} (default: F_ALLOW of the compute type).
+    Returns (value, mu): arrays of FP64 values and running error bounds in
+    units of u_c (default: the compute type's roundoff)."""
     inputs = [np.ascontiguousarray(x).reshape(-1, order="F") if x.ndim > 1 else
               np.ascontiguousarray(x) for x in inputs]
     n = inputs[0].size if inputs else 0
@@ -319,6 +378,10 @@ def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
         assert all(x.size == rows * cols for x in inputs)
     if u_c is None:
         u_c = compute_unit(dtype)
+    fa = F_ALLOW["f64" if dtype == "f64" else "f32"]
+    if f_allow is not None:
+        fa = dict(fa, **f_allow)
+    fop = np.array([fa[k] for k in F_ORDER], np.float64)
     op, a, b, lf, cst = expr.arrays()
     red = REDUCE[reduce]
     nout = {0: rows * cols, 1: 1, 2: cols, 3: rows, 4: 1}[red]
@@ -329,13 +392,13 @@ def evaluate(expr: E, inputs, dtype: str, shape=None, reduce=None, u_c=None,
     if views:
         rc = lib().or_eval_views(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
                                  lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
-                                 dts.ctypes.data, rows, cols, red, u_c, fexp, voff.ctypes.data,
+                                 dts.ctypes.data, rows, cols, red, u_c, fop.ctypes.data, voff.ctypes.data,
                                  vrs.ctypes.data, vcs.ctypes.data, out.ctypes.data,
                                  mu.ctypes.data)
     else:
         rc = lib().or_eval(op.size, op.ctypes.data, a.ctypes.data, b.ctypes.data,
                            lf.ctypes.data, cst.ctypes.data, len(inputs), _ptrs(inputs),
-                           dts.ctypes.data, rows, cols, red, u_c, fexp, out.ctypes.data,
+                           dts.ctypes.data, rows, cols, red, u_c, fop.ctypes.data, out.ctypes.data,
                            mu.ctypes.data)
     if rc != 0:
         raise ValueError("oracle evaluation failed (%d)" % rc)

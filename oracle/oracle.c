@@ -32,14 +32,25 @@
  *     leaf, exact constant: 0      constant not exact in u_c: |c|
  *     a +- b: mu_a + mu_b + |v|    a*b: mu_a|b| + |a|mu_b + |v|
  *     a/b: (mu_a + |v| mu_b)/|b| + |v|      -a, |a|: mu_a
- *     exp(a): |v|(mu_a + f)        sqrt(a): min(mu_a/(2|v|), sqrt(mu_a/u_c)) + |v|
- *     log(a): mu_a/|a| + f|v| + f   tanh(a): (1 - v^2) mu_a + f|v|
- *     pow(a, k) (k a constant): |k a^(k-1)| mu_a + f|v|
+ *     exp(a): |v|(mu_a + f_exp)    sqrt(a): spread(a, mu_a) + |v|
+ *     log(a): mu_a/|a| + f_log|v|   tanh(a): (1 - v^2) mu_a + f_tanh|v|
+ *     pow(a, k) (k a constant): |k a^(k-1)| mu_a + f_pow|v|
  *     a > b: 0 (1 or 0; the comparison itself is exact)
  *     conversion to FP32 storage: mu_a + |v|
  *     sum of n terms t_i: sum mu_i + (ceil(log2 n) + 2) sum |t_i|
- * where f is the allowance for a device transcendental (f = 2 allows 1 ulp;
- * log also gets an absolute allowance of f units, for results near 0).
+ * Each term is the first-order propagation of the operands' bounds through
+ * the operator's derivative plus the operator's own error.  sqrt propagates
+ * exactly instead (spread: the largest change of sqrt over the operand's
+ * error interval, see sqrt_spread), because its derivative is unbounded at 0
+ * and a cancellation just before it leaves an operand whose error is as
+ * large as its value; away from 0 spread is mu_a/(2|v|) to first order.  Correctly
+ * rounded operations (+ - * / sqrt, the conversion) contribute |v| (half an
+ * ulp is at most u_c |v|); a device elementary function contributes f |v|,
+ * where f (per function, in units of u_c relative to the result) is the
+ * caller's allowance fop[] = {f_exp, f_log, f_tanh, f_pow}.  The allowances
+ * are fixed by sweeping the device functions against libm (every FP32 input
+ * of each function's domain; a sample of FP64 inputs): f must be at least
+ * the largest relative error found there.
  *
  * Integer trees (u32) are evaluated in uint64 with every operation reduced
  * mod 2^32 (C unsigned semantics).
@@ -148,6 +159,25 @@ static void acc_final(const acc_t* a, int64_t nterms, double* out, double* mu) {
   *mu = a->mu + (ceil_log2(nterms) + 2.0) * a->abs;
 }
 
+/* Largest change of sqrt(a) when a (>= 0) moves by at most D = u_c * mu_a,
+ * in units of u_c.  sqrt is concave, so the worst move is downward unless it
+ * would cross zero; upward is worse only once D > 3a:
+ *   down = sqrt(a) - sqrt(a - D) = D / (sqrt(a) + sqrt(a - D))   (D <= a)
+ *        = sqrt(a)                                              (D > a)
+ *   up   = sqrt(a + D) - sqrt(a) = D / (sqrt(a + D) + sqrt(a)).
+ * For D << a this is the first-order term mu_a / (2 sqrt(a)); unlike that
+ * term it stays a bound when the operand's error is as large as the operand
+ * (a cancellation just before the square root). */
+static double sqrt_spread(double a, double mu_a, double u_c) {
+  if (!(a >= 0.0)) return NAN;
+  const double D = u_c * mu_a;
+  if (D == 0.0) return 0.0;
+  const double ra = sqrt(a);
+  const double down = D <= a ? D / (ra + sqrt(a - D)) : ra;
+  const double up = D / (sqrt(a + D) + ra);
+  return (down > up ? down : up) / u_c;
+}
+
 /* ---- one tree node over a chunk ---------------------------------------- */
 
 static int const_exact(double c, double u_c) {
@@ -173,7 +203,8 @@ static void eval_node(int k, const int32_t* op, const int32_t* ca,
                       const int32_t* cb, const int32_t* leaf, const double* cst,
                       const void* const* inputs, const int* dtypes, int64_t e0,
                       int64_t len, double** V, double** M, double u_c,
-                      double fexp, const views_t* vw) {
+                      const double* fop, const views_t* vw) {
+  const double f_exp = fop[0], f_log = fop[1], f_tanh = fop[2], f_pow = fop[3];
   double* v = V[k];
   double* m = M[k];
   const double* va = ca[k] >= 0 ? V[ca[k]] : NULL;
@@ -245,37 +276,35 @@ static void eval_node(int k, const int32_t* op, const int32_t* ca,
 #pragma omp parallel for schedule(static)
       for (i = 0; i < len; ++i) {
         v[i] = exp(va[i]);
-        m[i] = fabs(v[i]) * (ma[i] + fexp);
+        m[i] = fabs(v[i]) * (ma[i] + f_exp);
       }
       break;
     case OR_SQRT:
 #pragma omp parallel for schedule(static)
       for (i = 0; i < len; ++i) {
         v[i] = sqrt(va[i]);
-        double lin = v[i] != 0.0 ? ma[i] / (2.0 * fabs(v[i])) : INFINITY;
-        double hol = sqrt(ma[i] / u_c);
-        m[i] = (lin < hol ? lin : hol) + fabs(v[i]);
+        m[i] = sqrt_spread(va[i], ma[i], u_c) + fabs(v[i]);
       }
       break;
     case OR_LOG:
 #pragma omp parallel for schedule(static)
       for (i = 0; i < len; ++i) {
         v[i] = log(va[i]);
-        m[i] = ma[i] / fabs(va[i]) + fexp * fabs(v[i]) + fexp;
+        m[i] = ma[i] / fabs(va[i]) + f_log * fabs(v[i]);
       }
       break;
     case OR_TANH:
 #pragma omp parallel for schedule(static)
       for (i = 0; i < len; ++i) {
         v[i] = tanh(va[i]);
-        m[i] = (1.0 - v[i] * v[i]) * ma[i] + fexp * fabs(v[i]);
+        m[i] = (1.0 - v[i] * v[i]) * ma[i] + f_tanh * fabs(v[i]);
       }
       break;
     case OR_POW:  /* b is a constant exponent */
 #pragma omp parallel for schedule(static)
       for (i = 0; i < len; ++i) {
         v[i] = pow(va[i], vb[i]);
-        m[i] = fabs(vb[i] * pow(va[i], vb[i] - 1.0)) * ma[i] + fexp * fabs(v[i]);
+        m[i] = fabs(vb[i] * pow(va[i], vb[i] - 1.0)) * ma[i] + f_pow * fabs(v[i]);
       }
       break;
     case OR_GT:
@@ -318,22 +347,23 @@ static int check_tree(int n_nodes, const int32_t* op, const int32_t* a,
  *          OR_ROWSUM: out[n_rows], row sums
  *          OR_NORM:   out[0] = sqrt(sum of squares)
  * u_c: unit roundoff of the compute type the bound mu refers to.
- * fexp: mu allowance for exp (2 = one ulp).
+ * fop: allowances of the device elementary functions {exp, log, tanh, pow},
+ *      in units of u_c relative to the result (2 = one ulp at most).
  */
 int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
                   const int32_t* leaf, const double* cst, int n_inputs,
                   const void* const* inputs, const int* dtypes, int64_t n_rows,
-                  int64_t n_cols, int reduce, double u_c, double fexp,
+                  int64_t n_cols, int reduce, double u_c, const double* fop,
                   const int64_t* voff, const int64_t* vrs, const int64_t* vcs,
                   double* out, double* mu);
 
 int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
             const int32_t* leaf, const double* cst, int n_inputs,
             const void* const* inputs, const int* dtypes, int64_t n_rows,
-            int64_t n_cols, int reduce, double u_c, double fexp, double* out,
+            int64_t n_cols, int reduce, double u_c, const double* fop, double* out,
             double* mu) {
   return or_eval_views(n_nodes, op, a, b, leaf, cst, n_inputs, inputs, dtypes, n_rows, n_cols,
-                       reduce, u_c, fexp, NULL, NULL, NULL, out, mu);
+                       reduce, u_c, fop, NULL, NULL, NULL, out, mu);
 }
 
 /* or_eval with a view per node (voff/vrs/vcs indexed by node; only leaves
@@ -341,13 +371,13 @@ int or_eval(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
 int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_t* b,
                   const int32_t* leaf, const double* cst, int n_inputs,
                   const void* const* inputs, const int* dtypes, int64_t n_rows,
-                  int64_t n_cols, int reduce, double u_c, double fexp,
+                  int64_t n_cols, int reduce, double u_c, const double* fop,
                   const int64_t* voff, const int64_t* vrs, const int64_t* vcs,
                   double* out, double* mu) {
   const views_t vw = {voff, vrs, vcs, n_rows > 0 ? n_rows : 1};
   for (int q = 0; q < n_inputs; ++q)
     if (dtypes[q] < 0 || dtypes[q] > OR_U32) return OR_EBAD;
-  if (n_rows < 0 || n_cols < 0 || reduce < OR_NONE || reduce > OR_NORM) return OR_EBAD;
+  if (n_rows < 0 || n_cols < 0 || reduce < OR_NONE || reduce > OR_NORM || !fop) return OR_EBAD;
   if (!check_tree(n_nodes, op, a, b, leaf, n_inputs)) return OR_EBAD;
   const int64_t n = n_rows * n_cols;
 
@@ -371,7 +401,7 @@ int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_
   for (int64_t e0 = 0; e0 < n; e0 += chunk) {
     const int64_t len = (n - e0) < chunk ? (n - e0) : chunk;
     for (int k = 0; k < n_nodes; ++k)
-      eval_node(k, op, a, b, leaf, cst, inputs, dtypes, e0, len, V, M, u_c, fexp, &vw);
+      eval_node(k, op, a, b, leaf, cst, inputs, dtypes, e0, len, V, M, u_c, fop, &vw);
     const double* v = V[root];
     const double* m = M[root];
     if (reduce == OR_NONE) {
@@ -416,9 +446,7 @@ int or_eval_views(int n_nodes, const int32_t* op, const int32_t* a, const int32_
     double s, ms;
     acc_final(&col[0], n, &s, &ms);
     out[0] = sqrt(s);
-    double lin = out[0] != 0.0 ? ms / (2.0 * out[0]) : INFINITY;
-    double hol = sqrt(ms / u_c);
-    mu[0] = (lin < hol ? lin : hol) + out[0];
+    mu[0] = sqrt_spread(s, ms, u_c) + out[0];
   } else if (reduce == OR_COLSUM) {
     for (int64_t c = 0; c < n_cols; ++c) acc_final(&col[c], n_rows, &out[c], &mu[c]);
   } else if (reduce == OR_ROWSUM) {
