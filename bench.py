@@ -145,13 +145,23 @@ def copy_ceiling(fx, torch, stream, nbytes=1 << 31, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def read_flush(fx, torch, stream, nbytes=1 << 30):
+    """A function that streams `nbytes` (4x the 256 MB last-level cache)
+    through our read kernel: afterwards no line of anything else is cached,
+    and, unlike a write, it leaves no dirty lines whose write-back would
+    slow the next kernel."""
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    cfg = (256, 2, 16, 1024)
+    sink = torch.zeros(cfg[3], dtype=torch.float64, device="cuda")
+    return lambda: fx.fx_bw_read(buf, nbytes, sink, cfg=cfg, stream=stream)
+
+
 def cold_ms(torch, stream, fn, reps, flush):
-    """Median HIP-event time of fn() with `flush` overwritten before each
-    launch (outside the events): no input left in the 256 MB last-level
-    cache."""
+    """Median HIP-event time of fn() with flush() run before each launch
+    (outside the events): no input left in the 256 MB last-level cache."""
     times = []
     for _ in range(reps):
-        flush.fill_(1.0)
+        flush()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         fn()
@@ -159,6 +169,48 @@ def cold_ms(torch, stream, fn, reps, flush):
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b))
     return sorted(times)[len(times) // 2]
+
+
+def ceilings_detail(fx, torch, stream, reps=5):
+    """Bandwidth ceilings of this GPU from our own kernels, each timed cold
+    (a 1 GiB read before every launch, median of `reps`) at 2^28 FP32
+    elements (1 GiB) per array, best over a small launch sweep: read, write,
+    copy (1 read : 1 write) and triad (3 reads : 1 write, the mix of the
+    matrix workload's Z).  GB/s over the bytes each moves."""
+    n = 1 << 28
+    nb = 4 * n
+    bufs = [torch.empty(n, dtype=torch.float32, device="cuda").fill_(float(q + 1))
+            for q in range(4)]
+    # the read kernel writes one double per block: as many as the largest grid
+    grid_default = fx.fx_resolve_launch(0, fx.F32, (n, 1))[3]
+    sink = torch.zeros(max(grid_default, 4096), dtype=torch.float64, device="cuda")
+    flush = read_flush(fx, torch, stream)
+    cfgs = [None] + [(blk, ept, 16, grid) for blk in (256, 512) for ept in (1, 2, 4)
+                     for grid in (512, 1024, 2048, 4096)]
+    kinds = {
+        "read": (nb, lambda c, st: fx.fx_bw_read(bufs[0], nb, sink, cfg=c, stream=st)),
+        "write": (nb, lambda c, st: fx.fx_bw_write(bufs[3], nb, 7, cfg=c, stream=st)),
+        "copy": (2 * nb, lambda c, st: fx.fx_bw_copy(bufs[0], bufs[3], nb, cfg=c, stream=st)),
+        "triad": (4 * nb, lambda c, st: fx.fx_bw_triad(bufs[0], bufs[1], bufs[2], bufs[3], nb,
+                                                       False, cfg=c, stream=st)),
+        "triad_streaming_stores": (4 * nb, lambda c, st: fx.fx_bw_triad(
+            bufs[0], bufs[1], bufs[2], bufs[3], nb, True, cfg=c, stream=st)),
+    }
+    out = {}
+    with torch.cuda.stream(stream):
+        for name, (moved, fn) in kinds.items():
+            best = None
+            for c in cfgs:
+                if name == "copy" and c is not None and c[3] > 2048:
+                    continue
+                ms = cold_ms(torch, stream, lambda: fn(c, stream), reps, flush)
+                if best is None or ms < best[0]:
+                    best = (ms, c)
+            out[name] = {"GB/s": round(moved / (best[0] * 1e-3) / 1e9, 1),
+                         "ms": round(best[0], 4), "cfg": list(best[1]) if best[1] else "default"}
+    del bufs, sink
+    torch.cuda.empty_cache()
+    return out
 
 
 def event_ms(torch, stream, fn, reps):
@@ -178,7 +230,7 @@ def event_ms(torch, stream, fn, reps):
 def c1_detail(fx, torch, stream, reps):
     """The small vector workload, n = 2^20 FP32 (16 MiB: it fits the 256 MB
     last-level cache): Z = X%Y + 2W and accu(X%Y), and its u32 form
-    Z = (X^Y) + 3W, warm (back-to-back launches) and cold (a 512 MiB write
+    Z = (X^Y) + 3W, warm (back-to-back launches) and cold (a 1 GiB read
     between launches, outside the timed events)."""
     import synth
     n = 1 << 20
@@ -189,7 +241,7 @@ def c1_detail(fx, torch, stream, reps):
     ZU = torch.empty(n, dtype=torch.int32, device="cuda")
     s = torch.zeros(1, dtype=torch.float64, device="cuda")
     ws = fx.workspace(fx.R_ACCU, fx.F32, (n, 1))
-    flush = torch.empty(128 << 20, device="cuda")
+    flush = read_flush(fx, torch, stream)
     runs = {"z": (lambda: fx.fx_c1_z(X, Y, W, Z, stream=stream), 16 * n),
             "accu": (lambda: fx.fx_accu_xy(X, Y, s, ws, stream=stream), 8 * n),
             "u32_z": (lambda: fx.fx_c1_z(*U, ZU, stream=stream), 16 * n)}
@@ -199,7 +251,7 @@ def c1_detail(fx, torch, stream, reps):
             warm = event_ms(torch, stream, fn, reps)
             times = []
             for _ in range(reps):
-                flush.fill_(1.0)
+                flush()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
                 fn()
@@ -321,9 +373,11 @@ def paper_suite_detail(fx, torch, stream, reps):
 
 
 def modes_detail(fx, torch, stream, reps):
-    """One expression three ways: compile-time template (the fused kernel),
-    run-time tape (interpreter; also with the shipped launch model attached)
-    and run-time source (hipRTC-compiled at first use).  The matrix
+    """One expression four ways: compile-time template (the fused kernel),
+    run-time tape (interpreter; also with the shipped launch model attached),
+    run-time source (a tape's node list as text, hipRTC-compiled at first use)
+    and source generated at compile time from the template's own expression
+    type (hipRTC-compiled at first use).  The matrix
     workload's Z and its column sums over 2^26 FP32 elements, and the
     deepest of the first 200 generated tuning trees (depth <= 8) over 2^26
     elements."""
@@ -355,7 +409,10 @@ def modes_detail(fx, torch, stream, reps):
         **with_model(C2_NODES, ins[:3], Z, (n, 1)),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:3], Z, stream=stream), reps), 4),
-        "hiprtc_compile_ms": round(r.compile_ms(), 1)}
+        "hiprtc_compile_ms": round(r.compile_ms(), 1),
+        "et_source_compile_ms": round(fx.fx_source_prepare("c2_z", fx.F32), 1),
+        "et_source_ms": round(event_ms(torch, stream, lambda: fx.fx_source_eval(
+            "c2_z", ins[:3], Z, (ROWS, COLS), stream=stream), reps), 4)}
     cs = torch.empty(COLS, device="cuda")
     shape = (ROWS, COLS)
     ws = fx.workspace(fx.R_COLSUM, fx.F32, shape)
@@ -369,7 +426,10 @@ def modes_detail(fx, torch, stream, reps):
         **with_model(C2_NODES, ins[:3], cs, shape, fx.R_COLSUM),
         "runtime_source_ms": round(event_ms(torch, stream, lambda: r.eval(
             ins[:3], cs, shape, ws, stream=stream), reps), 4),
-        "hiprtc_compile_ms": round(r.compile_ms(), 1)}
+        "hiprtc_compile_ms": round(r.compile_ms(), 1),
+        "et_source_compile_ms": round(fx.fx_source_prepare("c2_colsum", fx.F32), 1),
+        "et_source_ms": round(event_ms(torch, stream, lambda: fx.fx_source_eval(
+            "c2_colsum", ins[:3], cs, shape, ws, stream=stream), reps), 4)}
     best = max((trees.tuning_item(5, i) for i in range(200)),
                key=lambda it: fx.Tape(it["nodes"]).info()["n_instructions"])
     k = best["n_inputs"]
@@ -475,6 +535,70 @@ def cpu_baseline(cols_sample=COLS, min_seconds=10.0, threads=None):
                       "in %.1f s (FP64, explicit temporaries)" % (cols_sample, reps, dt)}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo; lscpu reads the same)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_configs(min_seconds=3.0, threads=None):
+    """The FP64 oracle on bounded samples of the vector workload (2^20 FP32:
+    Z = X%Y + 2W, accu(X%Y), and the u32 Z = (X^Y) + 3W) and of the
+    precision workload (BF16 storage: Z = X%Y + 2W, accu(X%Y),
+    norm_fro(X-Y) and sum(X%Y, 0) over the first 256 of the 2^14 x 2^14
+    matrix's columns), each repeated for at least `min_seconds`; GB/s over
+    the same algorithmic bytes as the GPU kernels."""
+    import oracle
+    import synth
+    all_threads = oracle.num_threads()
+    if threads:
+        oracle.set_threads(threads)
+
+    def timed(fn, nbytes):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds:
+                return round(reps * nbytes / dt / 1e9, 3), reps, round(dt, 2)
+
+    out = {}
+    n = 1 << 20
+    x, y, w = [synth.fill(1, t, n, "f32") for t in range(3)]
+    u = [synth.fill(1, t, n, "u32", "uint31") for t in range(3)]
+
+    def c1():
+        oracle.evaluate(oracle.EXPRS["c1_z"], [x, y, w], "f32")
+        oracle.evaluate(oracle.EXPRS["xy"], [x, y], "f32", reduce="accu")
+        oracle.evaluate_u32(oracle.EXPRS["u32_z"], u)
+
+    v, reps, dt = timed(c1, 16 * n + 8 * n + 16 * n)
+    out["c1"] = {"GB/s": v, "sample": "2^20 FP32 Z, accu(X%%Y) and u32 Z: %d repetitions in "
+                 "%.1f s" % (reps, dt)}
+    side, cols = 1 << 14, 256
+    m = side * cols
+    xb, yb, wb = [synth.fill(3, t, m, "bf16") for t in range(3)]
+
+    def c3():
+        oracle.evaluate(oracle.EXPRS["c1_z"], [xb, yb, wb], "bf16")
+        oracle.evaluate(oracle.EXPRS["xy"], [xb, yb], "bf16", reduce="accu")
+        oracle.evaluate(oracle.EXPRS["diff"], [xb, yb], "bf16", shape=(side, cols), reduce="norm")
+        oracle.evaluate(oracle.EXPRS["xy"], [xb, yb], "bf16", shape=(side, cols), reduce="colsum")
+
+    v, reps, dt = timed(c3, (8 + 4 + 4 + 4) * m)
+    out["c3_bf16"] = {"GB/s": v, "sample": "BF16 Z, accu, norm_fro, sum(.,0) over 2^14 x 256 "
+                      "of the 2^14 x 2^14 matrix: %d repetitions in %.1f s" % (reps, dt)}
+    out["threads"] = oracle.num_threads()
+    oracle.set_threads(all_threads)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,16 +655,17 @@ def main():
     detail = {"fp32_fused": per}
     dominant_bytes = wl.bytes[dominant]
     achieved = dominant_bytes / (dms_live[dominant] * 1e-3) / 1e9
-    # the same kernels with a 512 MB write before each launch: the 1 GiB
+    # the same kernels with a 1 GiB read before each launch: the 1 GiB
     # working set of a warm step keeps part of itself in the last-level cache
     # (not in profile runs, whose per-kernel averages must be the steps')
     achieved_cold = None
     if not a.profile:
-        flush = torch.empty(128 << 20, device="cuda")
+        flush = read_flush(fx, torch, stream)
         with torch.cuda.stream(stream):
             cold = {r: cold_ms(torch, stream, lambda: wl.fused(r, stream), 11, flush)
                     for r in RESULTS}
         del flush
+        torch.cuda.empty_cache()
         for r in RESULTS:
             per[r]["cold_ms"] = round(cold[r], 5)
             per[r]["cold_GB/s"] = round(wl.bytes[r] / (cold[r] * 1e-3) / 1e9, 1)
@@ -576,6 +701,8 @@ def main():
         torch.cuda.empty_cache()
         log("bench: copy ceiling")
         detail["copy_ceiling_GB/s"] = round(copy_ceiling(fx, torch, stream), 1)
+        log("bench: read / write / copy / triad ceilings, cold, 2^28 elements")
+        detail["ceilings_cold_2^28"] = ceilings_detail(fx, torch, stream)
         log("bench: precision workload, 2^28 elements")
         detail["precision_2^28"] = precision_detail(fx, torch, stream, 20)
         torch.cuda.empty_cache()
@@ -610,11 +737,14 @@ def main():
     if not a.no_cpu:
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline()
+        cpu["cpu_model"] = cpu_model()
         if not a.no_extra:
             log("bench: CPU oracle on one core")
             one = cpu_baseline(cols_sample=COLS // 16, min_seconds=5.0, threads=1)
-            detail["cpu_oracle_1_core"] = {"value": one["value"], "unit": one["unit"],
-                                           "sample": one["sample"]}
+            cpu["one_core"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
+            log("bench: CPU oracle, vector and precision workloads")
+            cpu["other_configs"] = {"all_cores": cpu_oracle_configs(),
+                                    "one_core": cpu_oracle_configs(min_seconds=2.0, threads=1)}
 
     line = {
         "metric": "fused-expr HBM GB/s (% of peak) + speedup vs unfused, FP32 & BF16 storage",

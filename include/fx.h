@@ -90,6 +90,7 @@ typedef enum {
 /* Element-wise operators of the unfused baseline (one kernel each). */
 typedef enum {
   FX_OP_NEG = 1, FX_OP_ABS = 2, FX_OP_EXP = 3, FX_OP_SQRT = 4,      /* unary  */
+  FX_OP_LOG = 5, FX_OP_TANH = 6, /* unary, the paper's Sec. 4 expressions */
   FX_OP_ADD = 10, FX_OP_SUB = 11, FX_OP_SCHUR = 12, FX_OP_DIV = 13, /* binary */
   FX_OP_XOR = 14,                                                   /* u32    */
   FX_OP_SADD = 20,  /* k + A */
@@ -98,6 +99,8 @@ typedef enum {
   FX_OP_SRDIV = 23, /* k / A */
   FX_OP_SSUB = 24,  /* A - k */
   FX_OP_SRSUB = 25, /* k - A */
+  FX_OP_SPOW = 26,  /* pow(A, k); k = 1..4 evaluate as products of A, as in
+                       the fused expressions */
   FX_OP_LEAF = 30,  /* tape node: an input array     */
   FX_OP_CONST = 31  /* tape node: a scalar constant  */
 } fx_op;
@@ -232,7 +235,9 @@ int fx_addn(fx_dtype dt, const void* const* inputs, int32_t n, void* Z, fx_shape
  *     min(min(m - 1, n), min(m, n - 1)) (m - 1 for a square matrix).
  * Transposed operands are staged through LDS tiles so that every HBM read
  * stays coalesced.  dt: FX_F32, FX_F64 or FX_BF16.  A non-square input for
- * EXPR1/EXPR2 gives FX_E_SHAPE. */
+ * EXPR1/EXPR2 gives FX_E_SHAPE.  Z may not overlap an input read through a
+ * transposed, offset or diagonal view (FX_E_ARG, checked before anything is
+ * enqueued); only EXPR2's A and D, read in place, may be Z itself. */
 typedef enum {
   FX_PAPER_ADDSUB2 = 16,
   FX_PAPER_ADDSUB4 = 17,
@@ -251,7 +256,8 @@ int fx_paper_view_expr(int which, fx_dtype dt, const void* const* inputs, const 
  * The same skeletons and launch configurations as the fused calls, but each
  * operator writes a full temporary, as toolkits without fusion do (Sec. 4). */
 
-/* out = op(A), op in NEG/ABS/EXP/SQRT (ABS/NEG also for U32? no: FP only). */
+/* out = op(A), op in NEG/ABS/EXP/SQRT/LOG/TANH; floating-point dtypes only.
+ * Each is the device function that the fused expressions inline. */
 int fx_op_unary(int op, fx_dtype dt, const void* A, void* out, int64_t n,
                 const fx_launch* cfg, void* stream);
 
@@ -260,7 +266,7 @@ int fx_op_binary(int op, fx_dtype dt, const void* A, const void* B, void* out,
                  int64_t n, const fx_launch* cfg, void* stream);
 
 /* out = scalar op with k (FX_OP_S*), k rounded to the compute type
- * (for U32 it must be an integer in [0, 2^32)). */
+ * (for U32 it must be an integer in [0, 2^32); SPOW is floating point only). */
 int fx_op_scalar(int op, fx_dtype dt, const void* A, double k, void* out, int64_t n,
                  const fx_launch* cfg, void* stream);
 
@@ -402,6 +408,34 @@ double fx_rtc_compile_ms(const fx_rtc* r);
 int fx_rtc_eval(fx_rtc* r, const void* const* inputs, int32_t n_inputs, fx_shape shape, void* out,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* ---- kernels generated as source from expression types -------------------
+ * The paper's mechanism itself (Sec. 3): the library's workload expressions
+ * (FX_EXPR_*), the same C++ expression types that instantiate the fused
+ * entry points above, are walked at compile time and each becomes the full
+ * source text of one kernel, a string constant built during compilation and
+ * embedded in libfx.so.  At first use the driver (hipRTC) compiles it for the
+ * device; the code object is kept for the process (Sec. 4: that first
+ * compilation is the only overhead).  Every leaf occurrence is a kernel
+ * argument of its own and every scalar of the expression a run-time argument,
+ * as in the paper's generated kernels; loops, loads and reductions are the
+ * fused skeletons written as text (default launch configuration).
+ *
+ * fx_source_eval: evaluate expression `expr` over inputs {X, Y, W} (as the
+ * expression needs; `a` is the scalar of FX_EXPR_AXY_EXPW) of storage dtype
+ * dt and shape `shape`: Z (element-wise), one double (accu, norm_fro) or the
+ * column / row sums in the accumulator dtype, as fx_unfused() defines them;
+ * ws as for the fused calls.  Every array must be 16-byte aligned (FX_E_ARG
+ * otherwise).  FP dtypes; FX_U32 for FX_EXPR_C1_Z only.  The first call for
+ * an (expr, dt) compiles, which takes a while and needs hipRTC. */
+int fx_source_eval(int expr, fx_dtype dt, const void* const* inputs, double a, void* out,
+                   fx_shape shape, void* ws, size_t ws_bytes, void* stream);
+/* The generated text of (expr, dt): *len = its length; up to cap - 1 bytes
+ * and a terminating NUL are copied to buf (either may be NULL / 0). */
+int fx_source_text(int expr, fx_dtype dt, char* buf, size_t cap, size_t* len);
+/* Compile (expr, dt)'s text now if that has not happened (no GPU needed);
+ * *compile_ms (may be NULL) = milliseconds the compilation took. */
+int fx_source_prepare(int expr, fx_dtype dt, double* compile_ms);
+
 /* ---- batches: thousands of uneven expressions in one launch -------------
  * Every expression of a batch is a compiled tape over vectors.  The batch is
  * cut into fixed-size tiles (the tiles of one expression are consecutive);
@@ -519,8 +553,10 @@ int fx_model_create(int32_t n_features, int32_t hidden, const int32_t* head_size
                     int32_t n_heads, fx_model** out);
 int32_t fx_model_num_params(const fx_model* m);
 
-/* Host arrays (any may be NULL to keep the current values): parameters,
- * feature means and standard deviations (> 0).  New parameters reset Adam. */
+/* Host arrays (any may be NULL to keep the current values, trained ones
+ * included): parameters, feature means and standard deviations (> 0).  New
+ * parameters wait for queued training steps, then replace them and reset
+ * Adam.  Synchronous. */
 int fx_model_set(fx_model* m, const float* params, const float* mean, const float* stdv);
 /* Copy parameters / standardisation to host arrays (synchronous). */
 int fx_model_get(fx_model* m, float* params, float* mean, float* stdv);
@@ -554,9 +590,10 @@ int fx_model_grad(fx_model* m, const float* d_X, const int32_t* d_labels, int32_
 int fx_model_forward(const fx_model* m, const float* d_X, int32_t batch, float* d_logits,
                      int32_t* d_choice, void* stream);
 
-/* Host twin of the inference kernel for one feature row (no GPU): the same
- * FP32 fused multiply-add arithmetic in the same order.  Uses the parameters
- * as of the last fx_model_set / fx_model_get. */
+/* Host twin of the inference kernel for one feature row: the same FP32
+ * fused multiply-add arithmetic in the same order, on the host.  Uses the
+ * current parameters: after training steps it first waits for the device and
+ * copies them back once (a synchronisation); otherwise no GPU is involved. */
 int fx_model_choose(const fx_model* m, const float* features, int32_t* choice);
 
 void fx_model_destroy(fx_model* m);
@@ -591,7 +628,8 @@ int fx_model_predict(const fx_model* m, const float* features, int kind, fx_dtyp
  * calls on t that leave the launch configuration to the library (cfg NULL
  * or all zero) run the model's pick for their dtype, shape and kind
  * (fx_tape_features, then fx_model_predict, on the host; the last pick is
- * cached in the tape).  A pick whose workspace exceeds the call's ws_bytes
+ * cached in the tape until the dtype, shape or kind changes or the model is
+ * trained or set again).  A pick whose workspace exceeds the call's ws_bytes
  * falls back to the defaults.  Explicit configurations, fx_tune_time and
  * fx_autotune are unaffected.  m must stay alive while attached. */
 int fx_tape_set_model(fx_tape* t, const fx_model* m);
@@ -611,6 +649,14 @@ int fx_bw_read(const void* src, size_t bytes, double* sink, const fx_launch* cfg
 /* dst[i] = value for `bytes` bytes: write ceiling and cache flushing. */
 int fx_bw_write(void* dst, size_t bytes, uint32_t value, const fx_launch* cfg,
                 void* stream);
+
+/* dst = a + b + c over `bytes` bytes per array (u32 lanes, wrapping; every
+ * pointer 16-byte aligned, bytes a multiple of 16): the ceiling of a kernel
+ * that reads three streams for each one it writes.  flags: 1 = streaming
+ * (nontemporal) stores.  cfg: block, EPT (vectors in flight per array and
+ * thread) and grid as for element-wise calls. */
+int fx_bw_triad(const void* a, const void* b, const void* c, void* dst, size_t bytes, int flags,
+                const fx_launch* cfg, void* stream);
 
 #ifdef __cplusplus
 }

@@ -124,9 +124,11 @@ static void note(mr_stats* s, int64_t i, double rel, double ulp, int sub, double
 }
 
 /* got[i] is the device's FP32 result for the input whose bit pattern is
- * bits0 + i (i < count; the range must not wrap).  k: the exponent of pow. */
+ * bits0 + i (i < count; the range must not wrap).  k: the exponent of pow.
+ * max_abs_x > 0 restricts the sweep to inputs with |x| <= max_abs_x (the
+ * others, NaNs included, are skipped). */
 int mr_sweep_f32(int fn, uint32_t bits0, int64_t count, double k, const float* got,
-                 double f_allow, mr_stats* out) {
+                 double f_allow, double max_abs_x, mr_stats* out) {
   if (fn < MR_EXP || fn > MR_POW || count < 0 || (uint64_t)bits0 + (uint64_t)count > 4294967296ull)
     return -1;
   init(out);
@@ -139,6 +141,7 @@ int mr_sweep_f32(int fn, uint32_t bits0, int64_t count, double k, const float* g
       const uint32_t b = bits0 + (uint32_t)i;
       float x;
       memcpy(&x, &b, 4);
+      if (max_abs_x > 0 && !(fabs((double)x) <= max_abs_x)) continue;
       double y = ref64(fn, (double)x, k);
       /* a reference beyond FP32's rounding threshold to infinity is infinite
        * in FP32 (the FP64 libm value itself is finite there) */

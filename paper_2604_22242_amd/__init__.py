@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(HERE, "libfx.so")
 
 F32, F64, BF16, F16, U32 = 0, 1, 2, 3, 4
 R_ACCU, R_COLSUM, R_ROWSUM, R_NORM, R_DOT = 1, 2, 3, 4, 5
-OP = {"neg": 1, "abs": 2, "exp": 3, "sqrt": 4, "add": 10, "sub": 11, "schur": 12, "div": 13,
-      "xor": 14, "sadd": 20, "smul": 21, "sdiv": 22, "srdiv": 23, "ssub": 24, "srsub": 25,
-      "leaf": 30, "const": 31}
+OP = {"neg": 1, "abs": 2, "exp": 3, "sqrt": 4, "log": 5, "tanh": 6, "add": 10, "sub": 11,
+      "schur": 12, "div": 13, "xor": 14, "sadd": 20, "smul": 21, "sdiv": 22, "srdiv": 23,
+      "ssub": 24, "srsub": 25, "spow": 26, "leaf": 30, "const": 31}
 NODE_OP = dict(OP, mul=OP["schur"])  # tree nodes name the Schur product "mul"
 EXPR = {"c1_z": 1, "accu_xy": 2, "c2_z": 3, "c2_colsum": 4, "c2_rowsum": 5, "norm_diff": 6,
         "colsum_xy": 7, "axy_expw": 8}
@@ -120,6 +120,9 @@ _SIGS = {
     "fx_rtc_source": (_I, [_P, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "fx_rtc_compile_ms": (ctypes.c_double, [_P]),
     "fx_rtc_eval": (_I, [_P, ctypes.POINTER(_P), ctypes.c_int32, Shape, _P, _P, _SZ, _P]),
+    "fx_source_eval": (_I, [_I, _I, ctypes.POINTER(_P), _D, _P, Shape, _P, _SZ, _P]),
+    "fx_source_text": (_I, [_I, _I, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
+    "fx_source_prepare": (_I, [_I, _I, ctypes.POINTER(_D)]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
@@ -156,6 +159,7 @@ _SIGS = {
     "fx_bw_copy": (_I, [_P, _P, _SZ, _LP, _P]),
     "fx_bw_read": (_I, [_P, _SZ, _P, _LP, _P]),
     "fx_bw_write": (_I, [_P, _SZ, ctypes.c_uint32, _LP, _P]),
+    "fx_bw_triad": (_I, [_P, _P, _P, _P, _SZ, _I, _LP, _P]),
 }
 
 _lib = None
@@ -547,6 +551,32 @@ def fx_rtc_create(nodes, dt=F32, kind=0) -> Rtc:
     return Rtc(nodes, dt, kind)
 
 
+def fx_source_eval(expr, inputs, out, shape, ws=None, a=0.0, stream=None, dt=None):
+    """A workload expression (EXPR names or FX_EXPR_* codes) through its kernel
+    generated as source from the expression type (compiled at first use)."""
+    arr = (_P * 3)(*([_ptr(t) for t in inputs] + [None] * (3 - len(inputs))))
+    p, nb = _ws(ws)
+    dt = dtype_code(inputs[0]) if dt is None else dt
+    return check(lib().fx_source_eval(EXPR.get(expr, expr), dt, arr, float(a), _ptr(out),
+                                      _shape(shape), p, nb, _stream(stream)))
+
+
+def fx_source_text(expr, dt) -> str:
+    n = _SZ()
+    check(lib().fx_source_text(EXPR.get(expr, expr), dt, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    check(lib().fx_source_text(EXPR.get(expr, expr), dt, buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def fx_source_prepare(expr, dt) -> float:
+    """Compile (expr, dt)'s generated text if not yet done; returns the
+    milliseconds that compilation took."""
+    ms = _D()
+    check(lib().fx_source_prepare(EXPR.get(expr, expr), dt, ctypes.byref(ms)))
+    return ms.value
+
+
 def fx_rtc_source(r: Rtc) -> str:
     n = _SZ()
     check(lib().fx_rtc_source(r.handle, None, 0, ctypes.byref(n)))
@@ -845,3 +875,8 @@ def fx_bw_read(src, nbytes, sink, cfg=None, stream=None):
 
 def fx_bw_write(dst, nbytes, value=0, cfg=None, stream=None):
     return check(lib().fx_bw_write(_ptr(dst), nbytes, value, _cfg(cfg), _stream(stream)))
+
+
+def fx_bw_triad(a, b, c, dst, nbytes, streaming_stores=False, cfg=None, stream=None):
+    return check(lib().fx_bw_triad(_ptr(a), _ptr(b), _ptr(c), _ptr(dst), nbytes,
+                                   1 if streaming_stores else 0, _cfg(cfg), _stream(stream)))

@@ -66,21 +66,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
       for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x)
         z[i] = static_cast<T>(x.at(i));
     } else {
-      accum<C> acc;
+      lane_accum<C, N> acc;
       for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += step) {
         if (v0 - threadIdx.x + step <= nvec) {
           lanes<C, N> r[EPT];
           eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
-          acc.add(tile_sum<map_id, N, EPT>(r));
+          add_tile<map_id>(acc, r);
         } else {
 #pragma unroll
           for (int k = 0; k < EPT; ++k) {
             const int64_t v = v0 + k * blockDim.x;
-            if (v < nvec) acc.add(lane_sum<map_id, N>(x.template at_vec<N, kNT>(i0 + v * N)));
+            if (v < nvec) add_lanes<map_id>(acc, x.template at_vec<N, kNT>(i0 + v * N));
           }
         }
       }
-      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x) acc.add(x.at(i));
+      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x) acc.a[0].add(x.at(i));
       const double s = block_sum<double>(acc.value(), lds);
       if (d.n_tiles == 1) {
         if (threadIdx.x == 0) *static_cast<double*>(d.out) = s;

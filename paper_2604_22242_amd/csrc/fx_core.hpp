@@ -96,47 +96,51 @@ __device__ __forceinline__ void store_lanes(T* __restrict__ p, int64_t i, const 
 }
 
 // ---------------------------------------------------------------------------
-// Per-thread accumulation.  Floating point: Neumaier's compensated sum in
-// the compute type (s + c), handed upward in FP64.  Integers: plain u64.
+// Per-thread accumulation.  Floating point: Kahan's compensated sum in the
+// compute type, one compensated add per element (the running sum s and the
+// negated low-order part c that s has lost; the sum is s - c), handed upward
+// in FP64.  Its error is at most about 2u times the sum of the magnitudes of
+// the thread's terms, however many terms the thread adds.  Integers: plain
+// u64, exact.
 
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
 
-// `part` is the type in which a thread may pre-add a few of its terms
-// before handing their sum to add() (see tile_sum): the compute type for
-// floating point, u64 for u32 so that no pre-added sum wraps.
 template <class C> struct accum {
-  using part = C;
   C s = 0, c = 0;
   __device__ __forceinline__ void add(C t) {
 #pragma clang fp contract(off)
-    C u = s + t;
-    C e = (absv(s) >= absv(t)) ? (s - u) + t : (t - u) + s;
-    c += e;
+    const C y = t - c;
+    const C u = s + y;
+    c = (u - s) - y;
     s = u;
   }
-  __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+  // an infinite or NaN running sum is the sum (its compensation is NaN)
+  __device__ __forceinline__ double value() const {
+    return __builtin_isfinite(s) ? (double)s - (double)c : (double)s;
+  }
 };
 template <> struct accum<uint32_t> {
-  using part = uint64_t;
   uint64_t s = 0;
   __device__ __forceinline__ void add(uint64_t t) { s += t; }
   __device__ __forceinline__ uint64_t value() const { return s; }
 };
 
-// Sum of K values as a balanced pairwise tree (v is overwritten).  Each
-// term goes through at most ceil(log2 K) roundings, so a thread that
-// pre-adds its K values of a tile this way and hands the sum to the
-// compensated accumulator keeps the error within the sum's bound (a thread
-// never holds more terms than the whole reduction) at one compensated add
-// per tile instead of one per element.
-template <int K, class P> __device__ __forceinline__ P tree_sum(P (&v)[K]) {
+// A thread's compensated sums, one per vector lane: the elements at lane j
+// of the vectors a thread visits form chain j, added in the order the thread
+// visits its vectors.  Separate chains keep the dependent additions apart so
+// that they overlap (one long chain per thread is latency-bound when few
+// waves share a SIMD); the thread's sum is the chains' values added in FP64
+// in lane order.  Scalar tails join chain 0.
+template <class C, int N> struct lane_accum {
+  accum<C> a[N];
+  __device__ __forceinline__ auto value() const {
+    auto t = a[0].value();
 #pragma unroll
-  for (int w = 1; w < K; w *= 2)
-#pragma unroll
-    for (int i = 0; i + w < K; i += 2 * w) v[i] += v[i + w];
-  return v[0];
-}
+    for (int j = 1; j < N; ++j) t += a[j].value();
+    return t;
+  }
+};
 
 // Combination type above the thread: FP64 for floating point, u64 for u32.
 template <class C> struct wide { using type = double; };
@@ -228,6 +232,19 @@ struct launch {
 };
 
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// The library's default block size and EPT of a result kind (0 element-wise,
+// FX_R_*) for storage elements of `elem` bytes.  They do not depend on the
+// shape (the grid does), so generated kernel source can fix them in its text.
+constexpr int default_block(int kind, int elem) {
+  return kind == 0 ? 512
+       : kind == FX_R_COLSUM ? (elem >= 4 ? 512 : 256)
+       : kind == FX_R_ROWSUM ? (elem >= 4 ? 256 : 64)
+       : 256;  // full reductions
+}
+constexpr int default_ept(int kind, int elem) {
+  return kind == 0 ? 1 : kind == FX_R_COLSUM ? (elem >= 4 ? 2 : 1) : 2;
+}
 
 // Validate the user-facing fields (zeros mean "choose").
 int check_launch(const fx_launch* cfg);

@@ -1,5 +1,6 @@
 // Fused column and row sums of the matrix workload's expression.
 #include "fx_kernels.hpp"
+#include "fx_workloads.hpp"
 
 using namespace fx;
 
@@ -10,7 +11,7 @@ static int c2_dimsum(int kind, fx_dtype dt, const void* X, const void* Y, const 
     using T = typename decltype(t)::type;
     auto x = leaf<T>(X, s.n_rows, s.n_cols), y = leaf<T>(Y, s.n_rows, s.n_cols),
          w = leaf<T>(W, s.n_rows, s.n_cols);
-    return reduce_dim(kind, (x + y) % exp(-abs(w)) / (1 + x % x),
+    return reduce_dim(kind, c2_expr(x, y, w),
                       static_cast<acc_out_t<T>*>(out), ws, ws_bytes, cfg, S(stream));
   });
 }

@@ -92,8 +92,8 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
   if (!aligned16) vb = elem;
   L.vec_bytes = vb;
   if (ew || full) {
-    L.block = c.block ? c.block : ew ? 512 : 256;
-    L.ept = c.ept ? c.ept : ew ? 1 : 2;
+    L.block = c.block ? c.block : default_block(kind, elem);
+    L.ept = c.ept ? c.ept : default_ept(kind, elem);
     const int64_t tiles = std::max<int64_t>(1, ceil_div(n, (int64_t)L.block * L.ept * vec16));
     // full reductions: one ticket per block; below 2^24 elements the tickets
     // of two blocks per CU cost more than the extra bandwidth buys (measured:
@@ -109,8 +109,8 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
                                std::max<int64_t>(kReduceMinBlocks, tiles / kReduceMinTilesPerBlock));
     L.split = c.split ? c.split : (int)std::min<int64_t>(want, 1 << 30);
   } else if (kind == FX_R_COLSUM) {
-    L.block = c.block ? c.block : elem >= 4 ? 512 : 256;
-    L.ept = c.ept ? c.ept : elem >= 4 ? 2 : 1;
+    L.block = c.block ? c.block : default_block(kind, elem);
+    L.ept = c.ept ? c.ept : default_ept(kind, elem);
     if (!c.split && n_rows <= 32) {
       L.split = 0;  // thin columns: one thread per column
     } else {
@@ -121,8 +121,8 @@ launch resolve(int kind, int elem, int64_t n_rows, int64_t n_cols, const fx_laun
       L.split = (int)std::max<int64_t>(1, std::min<int64_t>(s, 65535));
     }
   } else {  // FX_R_ROWSUM
-    L.block = c.block ? c.block : elem >= 4 ? 256 : 64;
-    L.ept = c.ept ? c.ept : 2;
+    L.block = c.block ? c.block : default_block(kind, elem);
+    L.ept = c.ept ? c.ept : default_ept(kind, elem);
     const int64_t rblocks = std::max<int64_t>(1, ceil_div(n_rows, (int64_t)L.block * vec16));
     const int64_t target = cus * kRowsumWavesPerCU * 64 / L.block;
     int64_t s = c.split ? c.split : ceil_div(target, rblocks);

@@ -51,25 +51,20 @@ struct map_sq {
   __device__ static double finish(double s) { return ::sqrt(s); }
 };
 
-// The map M of a thread's EPT x N values of one tile, pre-added as a
-// pairwise tree in the accumulator's part type.
+// Add the map M of a thread's EPT x N values of one tile to its compensated
+// lane sums, one element at a time (lane j's chain takes vector 0's, then
+// vector 1's ... element j).
 template <class M, int N, int EPT, class C>
-__device__ __forceinline__ typename accum<C>::part tile_sum(const lanes<C, N> (&r)[EPT]) {
-  using P = typename accum<C>::part;
-  P v[EPT * N];
+__device__ __forceinline__ void add_tile(lane_accum<C, N>& acc, const lanes<C, N> (&r)[EPT]) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
 #pragma unroll
-    for (int j = 0; j < N; ++j) v[k * N + j] = static_cast<P>(M::f(r[k].v[j]));
-  return tree_sum<EPT * N>(v);
+    for (int j = 0; j < N; ++j) acc.a[j].add(M::f(r[k].v[j]));
 }
 template <class M, int N, class C>
-__device__ __forceinline__ typename accum<C>::part lane_sum(const lanes<C, N>& r) {
-  using P = typename accum<C>::part;
-  P v[N];
+__device__ __forceinline__ void add_lanes(lane_accum<C, N>& acc, const lanes<C, N>& r) {
 #pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = static_cast<P>(M::f(r.v[j]));
-  return tree_sum<N>(v);
+  for (int j = 0; j < N; ++j) acc.a[j].add(M::f(r.v[j]));
 }
 
 // EPT vectors of N elements at base, base + stride, ...: every leaf's loads
@@ -151,7 +146,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_full(E e, int64_t n, typename wid
   using C = typename E::ct;
   using D = typename wide<C>::type;
   __shared__ D lds[kMaxBlock / 64];
-  accum<C> acc;
+  lane_accum<C, N> acc;
   const int64_t nv = n / N;
   const int64_t tile = (int64_t)blockDim.x * EPT;
   // tile t exists while t * tile < nv (no 64-bit division: gfx950 has no
@@ -161,17 +156,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_full(E e, int64_t n, typename wid
     if ((t + 1) * tile <= nv) {
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, v0 * N, (int64_t)blockDim.x * N, r);
-      acc.add(tile_sum<M, N, EPT>(r));
+      add_tile<M>(acc, r);
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int64_t v = v0 + k * blockDim.x;
-        if (v < nv) acc.add(lane_sum<M, N>(e.template at_vec<N, kNT>(v * N)));
+        if (v < nv) add_lanes<M>(acc, e.template at_vec<N, kNT>(v * N));
       }
     }
   }
   if (N > 1 && blockIdx.x == gridDim.x - 1) {
-    for (int64_t i = nv * N + threadIdx.x; i < n; i += blockDim.x) acc.add(M::f(e.at(i)));
+    for (int64_t i = nv * N + threadIdx.x; i < n; i += blockDim.x) acc.a[0].add(M::f(e.at(i)));
   }
   D s = block_sum<D>(acc.value(), lds);
   if (gridDim.x == 1) {
@@ -211,19 +206,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_colsum(E e, int64_t n_rows, int s
   const int64_t r1 = min(n_rows, r0 + rpc);
   const int64_t base = col * n_rows + r0;
   const int64_t nv = r1 > r0 ? (r1 - r0) / N : 0;
-  accum<C> acc;
+  lane_accum<C, N> acc;
   const int64_t tile = (int64_t)blockDim.x * EPT;
   for (int64_t t0 = 0; t0 < nv; t0 += tile) {
     const int64_t v0 = t0 + threadIdx.x;
     if (t0 + tile <= nv) {
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, base + v0 * N, (int64_t)blockDim.x * N, r);
-      acc.add(tile_sum<map_id, N, EPT>(r));
+      add_tile<map_id>(acc, r);
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int64_t v = v0 + k * blockDim.x;
-        if (v < nv) acc.add(lane_sum<map_id, N>(e.template at_vec<N, kNT>(base + v * N)));
+        if (v < nv) add_lanes<map_id>(acc, e.template at_vec<N, kNT>(base + v * N));
       }
     }
   }
@@ -281,12 +276,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_rowsum(E e, int64_t n_rows, int64
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, r0 + c * n_rows, n_rows, r);
 #pragma unroll
-      for (int j = 0; j < N; ++j) {  // row j's EPT columns, pre-added
-        typename accum<C>::part v[EPT];
+      for (int j = 0; j < N; ++j)  // row j's EPT columns, in column order
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) v[k] = r[k].v[j];
-        acc[j].add(tree_sum<EPT>(v));
-      }
+        for (int k = 0; k < EPT; ++k) acc[j].add(r[k].v[j]);
     }
     for (; c < c1; ++c) {
       lanes<C, N> r = e.template at_vec<N, kNT>(r0 + c * n_rows);

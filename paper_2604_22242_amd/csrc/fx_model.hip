@@ -17,6 +17,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -180,8 +182,31 @@ struct fx_model {
   int32_t* perm = nullptr;  // fx_model_train's visiting order, `perm_cap` entries
   size_t perm_cap = 0;
   long step = 0;
-  std::vector<float> hP, hMean, hStd;  // host twin for single queries
+  // Host twin for single queries.  Training updates the parameters on the
+  // device only and marks the twin stale; it is refreshed (after the device
+  // has finished) before anything reads it.  `version` counts every change
+  // of the parameters or the standardisation, so cached picks can tell.
+  mutable std::mutex twin_mu;
+  mutable bool twin_stale = false;
+  mutable std::vector<float> hP;
+  std::vector<float> hMean, hStd;
+  std::atomic<long> version{0};
 };
+
+namespace fx {
+long model_version(const fx_model* m) { return m ? m->version.load() : 0; }
+}  // namespace fx
+
+// Bring the host twin of the parameters up to date (caller holds twin_mu).
+static int refresh_twin(const fx_model* m) {
+  if (!m->twin_stale) return FX_OK;
+  if (int rc = hip_check(hipDeviceSynchronize(), "model twin refresh")) return rc;
+  if (int rc = hip_check(hipMemcpy(m->hP.data(), m->dP, m->d.n_params() * sizeof(float),
+                                   hipMemcpyDeviceToHost), "model twin refresh"))
+    return rc;
+  m->twin_stale = false;
+  return FX_OK;
+}
 
 // Release paths cannot report errors: a failed hipFree here only means the
 // context is already gone.
@@ -268,32 +293,45 @@ int32_t fx_model_num_params(const fx_model* m) { return m ? m->d.n_params() : 0;
 int fx_model_set(fx_model* m, const float* params, const float* mean, const float* stdv) {
   if (!m) return fail(FX_E_ARG, "NULL model");
   const mlp_dims& d = m->d;
-  if (params) m->hP.assign(params, params + d.n_params());
-  if (mean) m->hMean.assign(mean, mean + d.F);
-  if (stdv) {
+  if (stdv)
     for (int f = 0; f < d.F; ++f)
       if (!(stdv[f] > 0.f)) return fail(FX_E_ARG, "standard deviation %d is not positive", f);
-    m->hStd.assign(stdv, stdv + d.F);
-  }
-  hipError_t e = hipMemcpy(m->dP, m->hP.data(), d.n_params() * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(m->dMean, m->hMean.data(), d.F * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(m->dStd, m->hStd.data(), d.F * sizeof(float), hipMemcpyHostToDevice);
-  if (params && e == hipSuccess) {  // a new starting point resets Adam
-    e = hipMemset(m->dM, 0, d.n_params() * sizeof(float));
+  std::lock_guard<std::mutex> g(m->twin_mu);
+  // only the arrays passed are written; the others keep their current values
+  // on the device (the host twin of the parameters may be stale then, and is
+  // refreshed when next read)
+  hipError_t e = hipSuccess;
+  if (params) {
+    e = hipDeviceSynchronize();  // queued training steps finish before the overwrite
+    m->hP.assign(params, params + d.n_params());
+    m->twin_stale = false;
+    if (e == hipSuccess)
+      e = hipMemcpy(m->dP, m->hP.data(), d.n_params() * sizeof(float), hipMemcpyHostToDevice);
+    // a new starting point resets Adam
+    if (e == hipSuccess) e = hipMemset(m->dM, 0, d.n_params() * sizeof(float));
     if (e == hipSuccess) e = hipMemset(m->dV, 0, d.n_params() * sizeof(float));
     m->step = 0;
   }
+  if (mean) {
+    m->hMean.assign(mean, mean + d.F);
+    if (e == hipSuccess)
+      e = hipMemcpy(m->dMean, m->hMean.data(), d.F * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (stdv) {
+    m->hStd.assign(stdv, stdv + d.F);
+    if (e == hipSuccess)
+      e = hipMemcpy(m->dStd, m->hStd.data(), d.F * sizeof(float), hipMemcpyHostToDevice);
+  }
+  m->version++;
   return hip_check(e, "fx_model_set");
 }
 
 int fx_model_get(fx_model* m, float* params, float* mean, float* stdv) {
   if (!m) return fail(FX_E_ARG, "NULL model");
   const mlp_dims& d = m->d;
-  if (int rc = hip_check(hipMemcpy(m->hP.data(), m->dP, d.n_params() * sizeof(float),
-                                   hipMemcpyDeviceToHost), "fx_model_get"))
-    return rc;
+  std::lock_guard<std::mutex> g(m->twin_mu);
+  m->twin_stale = true;  // read the device copy even if nothing was trained
+  if (int rc = refresh_twin(m)) return rc;
   if (params) memcpy(params, m->hP.data(), d.n_params() * sizeof(float));
   if (mean) memcpy(mean, m->hMean.data(), d.F * sizeof(float));
   if (stdv) memcpy(stdv, m->hStd.data(), d.F * sizeof(float));
@@ -326,6 +364,11 @@ static int model_step(fx_model* m, const float* X, const int32_t* labels, const 
   hipLaunchKernelGGL(k_mlp_params, dim3((np + 255) / 256), dim3(256), 0, st, d, (int)B, XN, Hs, DL,
                      DH, m->dP, m->dM, m->dV, d_grad, lr, beta1, beta2, eps, (float)c1, (float)c2,
                      RL, d_loss);
+  if (lr != 0.f) {  // the parameters change on the device
+    std::lock_guard<std::mutex> g(m->twin_mu);
+    m->twin_stale = true;
+    m->version++;
+  }
   return hip_check(hipGetLastError(), "k_mlp launch");
 }
 
@@ -411,6 +454,8 @@ int fx_model_forward(const fx_model* m, const float* d_X, int32_t batch, float* 
 int fx_model_choose(const fx_model* m, const float* x, int32_t* choice) {
   if (!m || !x || !choice) return fail(FX_E_ARG, "NULL argument");
   const mlp_dims& d = m->d;
+  std::lock_guard<std::mutex> g(m->twin_mu);
+  if (int rc = refresh_twin(m)) return rc;
   const float* P = m->hP.data();
   float xn[kMlpMaxF], h[kMlpMaxH], logit[kMlpMaxC];
   for (int f = 0; f < d.F; ++f) xn[f] = (x[f] - m->hMean[f]) / m->hStd[f];

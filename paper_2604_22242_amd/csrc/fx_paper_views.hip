@@ -34,6 +34,32 @@ int view_shape(int which, fx_shape s, fx_shape* out) {
   return fail(FX_E_ARG, "unknown view expression %d", which);
 }
 
+int view_inputs(int which) {
+  return which == FX_PAPER_ADDSUB4 || which == FX_PAPER_EXPR2 ? 4 : 2;
+}
+
+// The output may not overlap an input that is read through a transposed,
+// offset or diagonal view: a block would overwrite elements that another
+// block still has to read.  The only aliasing allowed is the element-wise
+// one of the global contract, for leaves read in place (A and D of expr2):
+// Z exactly equal to that input.
+int check_view_aliasing(int which, const void* const* in, const void* Z, fx_shape s, fx_shape o,
+                        size_t esize) {
+  const uintptr_t z0 = reinterpret_cast<uintptr_t>(Z);
+  const uintptr_t z1 = z0 + (uintptr_t)(o.n_rows * o.n_cols) * esize;
+  const uintptr_t bytes = (uintptr_t)(s.n_rows * s.n_cols) * esize;
+  for (int q = 0; q < view_inputs(which); ++q) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(in[q]);
+    if (!in[q]) return fail(FX_E_ARG, "NULL input %d", q);
+    if (a0 >= z1 || a0 + bytes <= z0) continue;
+    const bool in_place = which == FX_PAPER_EXPR2 && (q == 0 || q == 3) && a0 == z0;
+    if (!in_place)
+      return fail(FX_E_ARG, "the output overlaps input %d, which this expression reads through "
+                  "a transposed, offset or diagonal view", q);
+  }
+  return FX_OK;
+}
+
 template <class F> int with_view_dtype(fx_dtype dt, F&& f) {
   switch (dt) {
     case FX_F32: return f(tag<float>{});
@@ -65,6 +91,8 @@ int fx_paper_view_expr(int which, fx_dtype dt, const void* const* in, const doub
   const int64_t r0 = (m - o.n_rows) / 2, c0 = (n - o.n_cols) / 2;
   return with_view_dtype(dt, [&](auto t_) {
     using T = typename decltype(t_)::type;
+    if (!Z) return fail(FX_E_ARG, "NULL output pointer");
+    if (int rc = check_view_aliasing(which, in, Z, s, o, sizeof(T))) return rc;
     T* z = static_cast<T*>(Z);
     auto L = [&](int q) { return leaf<T>(in[q], m, n); };
     switch (which) {

@@ -373,8 +373,10 @@ int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
   fx_launch pick;
   {
     std::lock_guard<std::mutex> g(t->mu);
+    const long version = model_version(t->model);
     if (!(t->have_choice && t->choice_dt == dt && t->choice_kind == kind &&
-          t->choice_shape.n_rows == s.n_rows && t->choice_shape.n_cols == s.n_cols)) {
+          t->choice_shape.n_rows == s.n_rows && t->choice_shape.n_cols == s.n_cols &&
+          t->choice_version == version)) {
       float f[32];
       const int32_t nf = fx_tape_features(t, dt, s, kind, f, 32);
       if (nf < 0) return -nf;
@@ -383,6 +385,7 @@ int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
       t->choice_dt = dt;
       t->choice_kind = kind;
       t->choice_shape = s;
+      t->choice_version = version;
     }
     pick = t->choice;
   }

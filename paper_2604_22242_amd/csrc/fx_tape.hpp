@@ -349,10 +349,13 @@ struct fx_tape {
   mutable fx_dtype choice_dt = FX_F32;
   mutable fx_shape choice_shape{0, 0};
   mutable int choice_kind = 0;
+  mutable long choice_version = 0;  // the model's version the choice was made with
   mutable fx_launch choice{0, 0, 0, 0};
 };
 
 namespace fx {
+// Counts the changes of a model's parameters and standardisation.
+long model_version(const fx_model* m);
 // fx_tape_eval without the model: `cfg` as given (fx_tune_time times the
 // all-default configuration as the library's defaults).
 int tape_eval_exact(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,

@@ -21,6 +21,8 @@ int fx_op_unary(int op, fx_dtype dt, const void* A, void* out, int64_t n, const 
       case FX_OP_ABS: return eval(z, abs(a), cfg, S(stream));
       case FX_OP_EXP: return eval(z, exp(a), cfg, S(stream));
       case FX_OP_SQRT: return eval(z, sqrt(a), cfg, S(stream));
+      case FX_OP_LOG: return eval(z, log(a), cfg, S(stream));
+      case FX_OP_TANH: return eval(z, tanh(a), cfg, S(stream));
     }
     return fail(FX_E_ARG, "unknown unary operator %d", op);
   });
@@ -82,6 +84,7 @@ int fx_op_scalar(int op, fx_dtype dt, const void* A, double k, void* out, int64_
       case FX_OP_SRDIV: return eval(z, k / a, cfg, S(stream));
       case FX_OP_SSUB: return eval(z, a - k, cfg, S(stream));
       case FX_OP_SRSUB: return eval(z, k - a, cfg, S(stream));
+      case FX_OP_SPOW: return eval(z, pow(a, k), cfg, S(stream));
     }
     return fail(FX_E_ARG, "unknown scalar operator %d", op);
   });

@@ -26,7 +26,7 @@ DISTS = {"uniform": 0, "lognormal": 1, "uint31": 2, "ones": 3, "uniform12": 4}
 
 # Per-workload seeds and tensor ids (X=0, Y=1, W=2, further inputs 3, 4, ...).
 SEED = {"small": 1, "matrix": 2, "precision": 3, "batch": 4,
-        "tune_train": 5, "tune_heldout": 6}
+        "tune_train": 5, "tune_heldout": 6, "mathsweep": 7}
 TENSOR = {"X": 0, "Y": 1, "W": 2}
 
 

@@ -96,3 +96,26 @@ def test_unfused_temporaries(fx):
     assert fx.fx_unfused_tmp_bytes("c2_z", fx.F32, (8192, 8192)) == 2 * 8192 * 8192 * 4
     assert fx.fx_unfused_tmp_bytes("accu_xy", fx.BF16, (1000, 1)) == 2048
     assert fx.fx_unfused_tmp_bytes(99, fx.F32, (10, 1)) == 0
+
+
+def test_view_expressions_refuse_overlapping_outputs(fx):
+    """An output that overlaps an input read through a transposed, offset or
+    diagonal view is refused on the host (nothing is enqueued)."""
+    L = fx.lib()
+    m = n = 64
+    nbytes = m * n * 4
+    a, b, c, d = FAKE, FAKE + nbytes, FAKE + 2 * nbytes, FAKE + 3 * nbytes
+    sc = (ctypes.c_double * 1)(1.5)
+
+    def call(which, ins, z):
+        arr = (ctypes.c_void_p * 4)(*ins)
+        return L.fx_paper_view_expr(fx.PAPER_VIEW[which], fx.F32, arr, sc, z, fx.Shape(m, n), None)
+
+    assert call("expr1", [a, b, 0, 0], a) == 1                 # Z = X, read transposed
+    assert "overlaps input 0" in fx.fx_last_error()
+    assert call("expr1", [a, b, 0, 0], b + 4) == 1             # partial overlap with Y
+    assert call("expr2", [a, b, c, d], b) == 1                 # Z = B, read transposed
+    assert call("expr2", [a, b, c, d], a + 64) == 1            # partial overlap with A
+    assert call("addsub2", [a, b, 0, 0], a) == 1               # centre submatrix of X
+    assert call("addsub4", [a, b, c, d], d + 16) == 1
+    assert call("diagsum", [a, b, 0, 0], b + 8) == 1           # a diagonal of Y

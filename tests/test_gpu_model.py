@@ -299,3 +299,40 @@ def test_native_training_rejects_a_bad_order():
     with pytest.raises(fx.FxError):
         m.train(Xd, yd, 2, 4, 1e-3, bad)
     assert np.array_equal(m.get()[0], p)  # nothing ran
+
+
+def test_set_with_null_params_keeps_trained_parameters():
+    """After training, fx_model_set(NULL params, mean, std) must keep the
+    trained parameters, and the host twin (choose) must use them without an
+    explicit fx_model_get: choose agrees with the inference kernel."""
+    torch, fx = need_gpu()
+    rng = np.random.default_rng(9)
+    m, p, mean, std = _model(fx, rng)
+    X, y = _data(rng, 256)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    for _ in range(20):
+        m.train_step(Xd, yd, 5e-2)
+    torch.cuda.synchronize()
+    mean2 = (mean + 0.25).astype(np.float32)
+    m.set(None, mean2, std)                         # keep the trained parameters
+    trained = m.get()[0]
+    assert not np.array_equal(trained, p), "training did not move the parameters"
+    choice = torch.empty(256, len(HEADS), dtype=torch.int32, device="cuda")
+    logits = torch.empty(256, C, device="cuda")
+    m.forward(Xd, logits, choice)
+    torch.cuda.synchronize()
+    ref = _forward64(trained, X, mean2.astype(np.float64), std.astype(np.float64))
+    got = logits.cpu().numpy()
+    # FP32 forward against FP64: relative to the size of each row's logits
+    scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1.0)
+    assert np.max(np.abs(got - ref) / scale) < 1e-5
+    # and not the untrained parameters' logits
+    old = _forward64(p, X, mean2.astype(np.float64), std.astype(np.float64))
+    assert np.max(np.abs(got - old) / scale) > 1e-2
+    ch = choice.cpu().numpy()
+    m2, _, _, _ = _model(fx, np.random.default_rng(9))
+    for _ in range(20):
+        m2.train_step(Xd, yd, 5e-2)
+    m2.set(None, mean2, std)                        # no get(): the twin refreshes itself
+    for b in range(0, 256, 17):
+        assert m2.choose(X[b]) == list(ch[b])

@@ -96,6 +96,9 @@ def test_half_ops_round_once(dtype):
     if dtype == "bf16":   # the product of two bf16 values is exact in FP32
         want = torch.from_numpy((a * b).astype(np.float32)).to(torch.bfloat16).float().double()
         assert np.array_equal(from_dev(out, dtype), want.numpy())
+    else:                 # FP32: the exact (FP64) product rounded once
+        want = (a * b).astype(np.float32).astype(np.float64)
+        assert np.array_equal(from_dev(out, dtype), want)
 
 
 EXPRS = [("c1_z", "c1_z", None), ("c2_z", "c2_z", None), ("accu_xy", "xy", "accu"),
