@@ -369,6 +369,24 @@ int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as fx_tape_eval, same kernels and same bits for the same
+ * launch, with the reductions' workspace taken from a static device array
+ * of the library (16 MiB, one per GPU, held until the process ends) instead
+ * of a caller's.  The caller still passes inputs and outputs.  The launch is
+ * cfg, or the interpreter's defaults for fields left at 0; a model attached
+ * with fx_tape_set_model is not consulted.  A reduction whose
+ * fx_workspace_bytes exceeds 16 MiB gives FX_E_WORKSPACE before anything is
+ * enqueued.  The first call on a device looks the array's address up and
+ * clears it with a kernel on `stream`; every call leaves its finish counters
+ * at zero.  No call allocates: no hipMalloc, hipFree or allocating library
+ * routine.  All calls on one GPU share the array, so calls that may overlap
+ * on one GPU (different streams, or other host threads) race and must be
+ * serialised by the caller. */
+int fx_tape_eval_static(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
+                        fx_shape shape, int kind, void* out, const fx_launch* cfg, void* stream);
+
 /* ---- run-time source mode -------------------------------------------------
  * The paper's own mechanism (Sec. 3): the kernel source of an expression is
  * generated, compiled through the driver at first use and reused.  Here a

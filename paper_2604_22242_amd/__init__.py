@@ -125,6 +125,8 @@ _SIGS = {
     "fx_source_prepare": (_I, [_I, _I, ctypes.POINTER(_D)]),
     "fx_tape_eval": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _P, _SZ,
                           _LP, _P]),
+    "fx_tape_eval_static": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.c_int32, Shape, _I, _P, _LP,
+                                 _P]),
     "fx_batch_create": (_I, [ctypes.POINTER(BatchItem), ctypes.c_int32, _I, _LP, _I64,
                              ctypes.POINTER(_P)]),
     "fx_batch_launch": (_I, [_P, _P]),
@@ -516,6 +518,16 @@ def fx_tape_eval(tape: Tape, inputs, out, shape, kind=0, ws=None, cfg=None, stre
     p, nb = _ws(ws)
     return check(lib().fx_tape_eval(tape.handle, dt, arr, len(inputs), _shape(shape), kind,
                                     _ptr(out), p, nb, _cfg(cfg), _stream(stream)))
+
+
+def fx_tape_eval_static(tape: Tape, inputs, out, shape, kind=0, cfg=None, stream=None, dt=None):
+    """fx_tape_eval with the library's static device scratch as the
+    reductions' workspace: the call allocates nothing."""
+    arr = (_P * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    if dt is None:
+        dt = dtype_code(inputs[0]) if inputs else dtype_code(out)
+    return check(lib().fx_tape_eval_static(tape.handle, dt, arr, len(inputs), _shape(shape), kind,
+                                           _ptr(out), _cfg(cfg), _stream(stream)))
 
 
 # ---- run-time source mode ----------------------------------------------------------------
