@@ -2,14 +2,19 @@
 //
 // Host: each item's compiled program is copied into a device array, the
 // items are cut into fixed-size tiles (consecutive per item) and a tile
-// table maps tile -> item.  Device: a grid of persistent blocks strides over
-// the tiles; the program of a tile is read through a pointer (wave-uniform
-// loads), interpreted with the same TapeExpr code as fx_tape_eval, and
-// element-wise tiles write their slice of the output.  Reducing items
-// publish one FP64 partial per tile; the tile that draws the item's last
-// ticket adds the item's partials in tile order and resets the counter.
+// table maps tile -> item; the table lists tiles by decreasing estimated
+// cost (device operations x elements), so that the work queue hands out the
+// long tiles first and the short ones fill the end.  Device: a grid of
+// persistent blocks takes tiles from that queue (one atomic ticket per tile);
+// the program of a tile is read through a pointer (wave-uniform loads) and
+// interpreted with the same TapeExpr code as fx_tape_eval, element-wise
+// tiles write their slice of the output and reducing items publish one FP64
+// partial per tile; the tile that draws the item's last ticket adds the
+// item's partials in tile order and resets the counter.  The last block to
+// leave resets the queue, so the launch can be replayed as it is.
 #include <algorithm>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "fx_tape.hpp"
@@ -25,76 +30,142 @@ struct batch_desc {
   int64_t first_tile;
 };
 
+// One tile of the queue: its item and its index within the item.
+struct batch_tile {
+  uint32_t item, index;
+};
+
+// Inputs of EPT vectors at base + k * stride, of which only the elements
+// below `end` exist (the last pass of an item): whole vectors load as
+// vectors, the vector that straddles `end` element by element.
+template <int N, int EPT, class X>
+__device__ __forceinline__ void batch_load_tail(const X& x, int n_in, int64_t base, int64_t stride,
+                                                int64_t end,
+                                                lanes<typename X::ct, N> (&in)[EPT][kTapeMaxIn]) {
+  using C = typename X::ct;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int64_t e = base + k * stride;
+#pragma unroll
+    for (int q = 0; q < kTapeMaxIn; ++q) {
+      if (q < n_in && e + N <= end) {
+        in[k][q] = load_lanes<N, kNT>(x.p[q], e);
+      } else {
+        in[k][q] = unset_lanes<C, N>();
+        if (q < n_in)
+#pragma unroll
+          for (int j = 0; j < N; ++j)
+            if (e + j < end) in[k][q].v[j] = static_cast<C>(x.p[q][e + j]);
+      }
+    }
+  }
+}
+
 template <class T, int N, int EPT, int SLOTS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restrict__ descs,
                                                    const tape_prog* __restrict__ progs,
-                                                   const uint32_t* __restrict__ tile_item,
+                                                   const batch_tile* __restrict__ tiles,
                                                    int64_t n_tiles, int64_t tile_elems,
                                                    double* __restrict__ partials,
-                                                   unsigned* __restrict__ counters) {
+                                                   unsigned* __restrict__ counters,
+                                                   unsigned* __restrict__ queue) {
   using C = ct_t<T>;
   __shared__ double lds[kMaxBlock / 64];
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const uint32_t it = tile_item[t];
-    const batch_desc d = descs[it];
+  __shared__ unsigned next;
+  const int64_t stride = (int64_t)blockDim.x * N;  // between a thread's vectors
+  const int64_t pass = stride * EPT;               // elements per block pass
+  for (;;) {
+    if (threadIdx.x == 0)
+      next = __hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned t = next;
+    __syncthreads();  // every thread has read `next` before it changes
+    if (t >= n_tiles) break;
+    const batch_tile tl = tiles[t];
+    const batch_desc d = descs[tl.item];
     TapeExpr<T, true, SLOTS> x;
 #pragma unroll
     for (int q = 0; q < kTapeMaxIn; ++q) x.p[q] = static_cast<const T*>(d.in[q]);
     x.n_rows = d.n;
     x.n_cols = 1;
-    x.prog = progs + it;
-    const int64_t i0 = (t - d.first_tile) * tile_elems;
+    x.prog = progs + tl.item;
+    const int n_in = x.P().n_in;
+    const bool ew = d.kind == 0;
+    T* z = static_cast<T*>(d.out);
+    const int64_t i0 = (int64_t)tl.index * tile_elems;
     const int64_t i1 = min(d.n, i0 + tile_elems);
-    const int64_t nvec = (i1 - i0) / N;  // i0 is a multiple of N
-    const int64_t step = (int64_t)blockDim.x * EPT;
-    if (d.kind == 0) {
-      T* z = static_cast<T*>(d.out);
-      for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += step) {
-        if (v0 - threadIdx.x + step <= nvec) {
-          lanes<C, N> r[EPT];
-          eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
+    lane_accum<C, N> acc;
+    for (int64_t e0 = i0; e0 < i1; e0 += pass) {
+      const int64_t base = e0 + (int64_t)threadIdx.x * N;
+      const bool whole = e0 + pass <= i1;  // uniform
+      lanes<C, N> in[EPT][kTapeMaxIn];
+      if (whole) {
 #pragma unroll
-          for (int k = 0; k < EPT; ++k) store_lanes<N, kNTS>(z, i0 + (v0 + k * blockDim.x) * N, r[k]);
-        } else {
+        for (int q = 0; q < kTapeMaxIn; ++q)
 #pragma unroll
-          for (int k = 0; k < EPT; ++k) {
-            const int64_t v = v0 + k * blockDim.x;
-            if (v < nvec) store_lanes<N, kNTS>(z, i0 + v * N, x.template at_vec<N, kNT>(i0 + v * N));
-          }
-        }
-      }
-      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x)
-        z[i] = static_cast<T>(x.at(i));
-    } else {
-      lane_accum<C, N> acc;
-      for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += step) {
-        if (v0 - threadIdx.x + step <= nvec) {
-          lanes<C, N> r[EPT];
-          eval_tile<N, EPT>(x, i0 + v0 * N, (int64_t)blockDim.x * N, r);
-          add_tile<map_id>(acc, r);
-        } else {
-#pragma unroll
-          for (int k = 0; k < EPT; ++k) {
-            const int64_t v = v0 + k * blockDim.x;
-            if (v < nvec) add_lanes<map_id>(acc, x.template at_vec<N, kNT>(i0 + v * N));
-          }
-        }
-      }
-      for (int64_t i = i0 + nvec * N + threadIdx.x; i < i1; i += blockDim.x) acc.a[0].add(x.at(i));
-      const double s = block_sum<double>(acc.value(), lds);
-      if (d.n_tiles == 1) {
-        if (threadIdx.x == 0) *static_cast<double*>(d.out) = s;
+          for (int k = 0; k < EPT; ++k)
+            in[k][q] = q < n_in ? load_lanes<N, kNT>(x.p[q], base + k * stride) : unset_lanes<C, N>();
       } else {
-        if (threadIdx.x == 0) publish(partials + t, s);
-        if (take_last_ticket(counters + it, d.n_tiles)) {
-          if (threadIdx.x == 0) {
-            *static_cast<double*>(d.out) = sum_strided<double>(partials + d.first_tile, 1, d.n_tiles);
-            reset_counter(counters + it);
+        batch_load_tail<N, EPT>(x, n_in, base, stride, i1, in);
+      }
+      // one interpreter for whole and partial passes
+      lanes<C, N * EPT> flat[kTapeMaxIn];
+#pragma unroll
+      for (int q = 0; q < kTapeMaxIn; ++q)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+#pragma unroll
+          for (int j = 0; j < N; ++j) flat[q].v[k * N + j] = in[k][q].v[j];
+      const lanes<C, N * EPT> r = x.template interpret<N * EPT>(flat);
+      if (whole) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          lanes<C, N> v;
+#pragma unroll
+          for (int j = 0; j < N; ++j) v.v[j] = r.v[k * N + j];
+          if (ew) store_lanes<N, kNTS>(z, base + k * stride, v);
+          else add_lanes<map_id>(acc, v);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int64_t e = base + k * stride;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            if (e + j < i1) {
+              if (ew) z[e + j] = static_cast<T>(r.v[k * N + j]);
+              else acc.a[j].add(r.v[k * N + j]);
+            }
           }
         }
       }
     }
-    __syncthreads();  // the next tile reuses lds
+    if (!ew) {
+      const double s = block_sum<double>(acc.value(), lds);
+      if (d.n_tiles == 1) {
+        if (threadIdx.x == 0) *static_cast<double*>(d.out) = s;
+      } else {
+        const int64_t pt = d.first_tile + tl.index;  // partials in tile order per item
+        if (threadIdx.x == 0) publish(partials + pt, s);
+        if (take_last_ticket(counters + tl.item, d.n_tiles)) {
+          if (threadIdx.x == 0) {
+            *static_cast<double*>(d.out) = sum_strided<double>(partials + d.first_tile, 1, d.n_tiles);
+            reset_counter(counters + tl.item);
+          }
+        }
+      }
+      __syncthreads();  // the next tile reuses lds
+    }
+  }
+  // the last block out resets the queue for the next launch (every block's
+  // final ticket, which found the queue empty, precedes its exit ticket)
+  if (threadIdx.x == 0) {
+    const unsigned done = __hip_atomic_fetch_add(queue + 1, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(queue + 1, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -111,9 +182,10 @@ struct fx_batch {
   void* d_ws = nullptr;
   batch_desc* d_descs = nullptr;
   tape_prog* d_progs = nullptr;
-  uint32_t* d_tiles = nullptr;
+  batch_tile* d_tiles = nullptr;
   double* d_partials = nullptr;
   unsigned* d_counters = nullptr;
+  unsigned* d_queue = nullptr;  // tile tickets, exit tickets (zero between launches)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
@@ -131,6 +203,7 @@ static void batch_free(fx_batch* b) {
   (void)hipFree(b->d_tiles);
   (void)hipFree(b->d_partials);
   (void)hipFree(b->d_counters);
+  (void)hipFree(b->d_queue);
   (void)hipFree(b->d_ws);
 }
 
@@ -163,11 +236,11 @@ static int batch_run(fx_batch* b, hipStream_t st) {
     if (b->small_slots)
       hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeSmallSlots>), dim3(I.grid), dim3(I.block), 0, st,
                          b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
-                         b->d_partials, b->d_counters);
+                         b->d_partials, b->d_counters, b->d_queue);
     else
       hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeMaxSlots>), dim3(I.grid), dim3(I.block), 0, st,
                          b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
-                         b->d_partials, b->d_counters);
+                         b->d_partials, b->d_counters, b->d_queue);
     return hip_check(hipGetLastError(), "k_batch launch");
   });
 }
@@ -208,17 +281,24 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   I = fx_batch_info{};
   I.count = count;
   I.block = c.block ? c.block : 256;
-  I.ept = c.ept ? c.ept : 2;  // two vectors per thread: one interpreter pass of 8 lanes
   I.vec_bytes = (c.vec_bytes ? std::max(c.vec_bytes, elem) : 16);
   if (addr_or & 15) I.vec_bytes = elem;  // every pointer must be 16-byte aligned for vectors
   b->vec = I.vec_bytes / elem;
+  // default: as many vectors per thread as fill one interpreter pass (8
+  // FP32-compute lanes, 4 FP64), at most 2
+  {
+    const int pass_lanes = elem == 8 ? kPassLanes<double, kTapeSmallSlots>
+                                     : kPassLanes<float, kTapeSmallSlots>;
+    I.ept = c.ept ? c.ept : std::max(1, std::min(2, pass_lanes / b->vec));
+  }
   const int64_t pass = (int64_t)I.block * I.ept * b->vec;
   const int64_t want = tile_elems ? tile_elems : 16384;
   I.tile_elems = ceil_div(want, pass) * pass;
   // tile table
   std::vector<batch_desc> descs(count);
   std::vector<tape_prog> progs(count);
-  std::vector<uint32_t> tiles;
+  std::vector<batch_tile> tiles;
+  std::vector<double> cost;
   int64_t first = 0;
   for (int i = 0; i < count; ++i) {
     const fx_batch_item& it = items[i];
@@ -236,12 +316,27 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     }
     d.n_tiles = (int32_t)nt;
     d.first_tile = first;
-    for (int64_t k = 0; k < nt; ++k) tiles.push_back((uint32_t)i);
+    for (int64_t k = 0; k < nt; ++k) {
+      tiles.push_back(batch_tile{(uint32_t)i, (uint32_t)k});
+      // device operations and memory streams per element, times the elements
+      const int64_t elems = std::min(it.n - k * I.tile_elems, I.tile_elems);
+      cost.push_back((double)elems *
+                     (it.tape->prog.n_ins + 2.0 * (it.tape->prog.n_in + (it.kind == 0 ? 1 : 0))));
+    }
     first += nt;
     progs[i] = it.tape->prog;
     I.bytes += (int64_t)elem * it.n * (it.tape->prog.n_in + (it.kind == 0 ? 1 : 0));
   }
   I.n_tiles = first;
+  {  // the queue hands out the costliest tiles first (ties: table order)
+    std::vector<int64_t> order(tiles.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    std::vector<batch_tile> sorted(tiles.size());
+    for (size_t q = 0; q < order.size(); ++q) sorted[q] = tiles[order[q]];
+    tiles.swap(sorted);
+  }
   const int64_t grid_default = (int64_t)device_cus() * 8;
   I.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(c.split ? c.split : grid_default,
                                                           std::max<int64_t>(1, I.n_tiles)));
@@ -261,17 +356,19 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   };
   alloc((void**)&b->d_descs, sizeof(batch_desc) * std::max(1, count));
   alloc((void**)&b->d_progs, sizeof(tape_prog) * std::max(1, count));
-  alloc((void**)&b->d_tiles, sizeof(uint32_t) * std::max<int64_t>(1, I.n_tiles));
+  alloc((void**)&b->d_tiles, sizeof(batch_tile) * std::max<int64_t>(1, I.n_tiles));
   alloc((void**)&b->d_partials, sizeof(double) * std::max<int64_t>(1, I.n_tiles));
   alloc((void**)&b->d_counters, sizeof(unsigned) * std::max(1, count));
+  alloc((void**)&b->d_queue, 2 * sizeof(unsigned));
   if (e == hipSuccess && count)
     e = hipMemcpy(b->d_descs, descs.data(), sizeof(batch_desc) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess && count)
     e = hipMemcpy(b->d_progs, progs.data(), sizeof(tape_prog) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess && I.n_tiles)
-    e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint32_t) * I.n_tiles, hipMemcpyHostToDevice);
+    e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(batch_tile) * I.n_tiles, hipMemcpyHostToDevice);
   alloc(&b->d_ws, std::max<size_t>(256, ws_total));
   if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(unsigned) * std::max(1, count));
+  if (e == hipSuccess) e = hipMemset(b->d_queue, 0, 2 * sizeof(unsigned));
   if (e == hipSuccess) e = hipMemset(b->d_ws, 0, std::max<size_t>(256, ws_total));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {

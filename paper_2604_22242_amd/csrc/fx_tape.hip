@@ -54,7 +54,7 @@ struct compiler {
   std::vector<operand> result;
   std::vector<int> free_slots;
   int next_slot = 0, max_slot = 0;
-  tape_prog* prog;
+  tape_code* prog;
   int status = FX_OK;
 
   int alloc() {
@@ -193,7 +193,7 @@ struct compiler {
 // a plain "LD b" followed by an instruction that reads the accumulator is
 // folded into it as the load-in modifier (slot b in the high byte of a).
 // Each removed instruction saves one fetch and one dispatch per lane group.
-void fuse_loads(tape_prog* p) {
+void fuse_loads(tape_code* p) {
   int o = 0;
   for (int i = 0; i < p->n_ins; ++i) {
     tape_ins I = p->ins[i];
@@ -224,7 +224,7 @@ void fuse_loads(tape_prog* p) {
 
 }  // namespace
 
-int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info* info) {
+int tape_compile(const fx_node* nodes, int32_t n, tape_code* prog, fx_tape_info* info) {
   if (!nodes || n <= 0) return fail(FX_E_ARG, "empty tree");
   if (n > 4 * kTapeMaxIns) return fail(FX_E_UNSUPPORTED, "tree of %d nodes is too large", n);
   compiler c;
@@ -266,7 +266,7 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
     }
   }
   c.uses[n - 1]++;  // the root's value is the output
-  *prog = tape_prog{};
+  *prog = tape_code{};
   prog->n_in = c.n_in;
   c.next_slot = c.max_slot = c.n_in;
   c.prog = prog;
@@ -287,6 +287,92 @@ int tape_compile(const fx_node* nodes, int32_t n, tape_prog* prog, fx_tape_info*
     if (nodes[k].op == FX_OP_CONST) info->n_consts++;
     else if (nodes[k].op != FX_OP_LEAF) info->op_count[op_index(nodes[k].op)]++;
   }
+  return FX_OK;
+}
+
+// Lower the architectural program into device micro-operations.  Every
+// micro-operation performs exactly the IEEE operations of the instruction it
+// comes from, so the two forms give the same bits:
+//   a folded load (LD_IN) becomes LD of that slot; STLD becomes ST then LD;
+//   abs / neg input modifiers become ABS / NEG, except where the consumer
+//   takes them as an operand modifier: exp(-|a|), sqrt(|a|), |a| + k;
+//   "0 - |a|" directly followed by exp becomes exp(-|a|) (0 - |a| and -|a|
+//   differ only in the sign of a zero result, which exp maps to 1 either way);
+//   acc - k becomes acc + (-k) (IEEE defines x - y as x + (-y)).
+int tape_lower(const tape_code& code, tape_prog* prog) {
+  *prog = tape_prog{};
+  prog->n_in = code.n_in;
+  prog->n_slots = code.n_slots <= kTapeSmallSlots ? kTapeSmallSlots : kTapeMaxSlots;
+  int n = 0;
+  auto emit = [&](uint8_t op, double k = 0.0) -> bool {
+    if (n >= kTapeMaxUops) return false;
+    tape_uop& u = prog->ins[n++];
+    u = tape_uop{};
+    u.op = op;
+    if (op >= U_LDI && op != U_NEG && op != U_ABS && op != U_EXP && op != U_SQRT &&
+        op != U_EXP_NABS && op != U_SQRT_ABS) {
+      int ki = -1;  // FP64 immediates, deduplicated by bit pattern
+      for (int c = 0; c < prog->n_consts; ++c)
+        if (__builtin_memcmp(&prog->kd[c], &k, sizeof k) == 0) ki = c;
+      if (ki < 0) {
+        if (prog->n_consts >= kTapeMaxConsts) return false;
+        ki = prog->n_consts++;
+        prog->kd[ki] = k;
+      }
+      u.ki = (uint8_t)ki;
+      u.kf = (float)k;
+    }
+    return true;
+  };
+  bool ok = true;
+  for (int i = 0; i < code.n_ins && ok; ++i) {
+    const tape_ins& I = code.ins[i];
+    const int op = I.op & 0xFF;
+    const int a = I.a & 0xFF, a2 = I.a >> 8;
+    const bool ld_in = (I.op & kLdIn) != 0, abs_in = (I.op & kAbsIn) != 0,
+               neg_in = (I.op & kNegIn) != 0;
+    const double k = I.kd;
+    if (ld_in) ok = ok && emit(U_LD + a2);
+    // consumers that take the modifiers as operand modifiers
+    if (op == A_EXP && abs_in && neg_in) { ok = ok && emit(U_EXP_NABS); continue; }
+    if (op == A_SQRT && abs_in && !neg_in) { ok = ok && emit(U_SQRT_ABS); continue; }
+    if (op == A_ADD_I && abs_in && !neg_in) { ok = ok && emit(U_ADDI_ABS, k); continue; }
+    if (op == A_RSUB_I && k == 0.0 && abs_in && !neg_in && i + 1 < code.n_ins &&
+        code.ins[i + 1].op == A_EXP) {
+      ok = ok && emit(U_EXP_NABS);
+      ++i;
+      continue;
+    }
+    if (abs_in) ok = ok && emit(U_ABS);
+    if (neg_in) ok = ok && emit(U_NEG);
+    switch (op) {
+      case A_LD: ok = ok && emit(U_LD + a); break;
+      case A_LDI: ok = ok && emit(U_LDI, k); break;
+      case A_ST: ok = ok && emit(U_ST + a); break;
+      case A_STLD: ok = ok && emit(U_ST + a) && emit(U_LD + a2); break;
+      case A_ADD_S: ok = ok && emit(U_ADD + a); break;
+      case A_SUB_S: ok = ok && emit(U_SUB + a); break;
+      case A_RSUB_S: ok = ok && emit(U_RSUB + a); break;
+      case A_MUL_S: ok = ok && emit(U_MUL + a); break;
+      case A_DIV_S: ok = ok && emit(U_DIV + a); break;
+      case A_RDIV_S: ok = ok && emit(U_RDIV + a); break;
+      case A_ADD_I: ok = ok && emit(U_ADDI, k); break;
+      case A_SUB_I: ok = ok && emit(U_ADDI, -k); break;
+      case A_RSUB_I: ok = ok && emit(U_RSUBI, k); break;
+      case A_MUL_I: ok = ok && emit(U_MULI, k); break;
+      case A_DIV_I: ok = ok && emit(U_DIVI, k); break;
+      case A_RDIV_I: ok = ok && emit(U_RDIVI, k); break;
+      case A_NEG: ok = ok && emit(U_NEG); break;
+      case A_ABS: ok = ok && emit(U_ABS); break;
+      case A_EXP: ok = ok && emit(U_EXP); break;
+      case A_SQRT: ok = ok && emit(U_SQRT); break;
+      default: return fail(FX_E_ARG, "instruction %d: unknown opcode %d", i, op);
+    }
+  }
+  if (!ok)
+    return fail(FX_E_UNSUPPORTED, "tape lowers to more than %d device operations or %d constants",
+                kTapeMaxUops, kTapeMaxConsts);
+  prog->n_ins = n;  // ins[n] stays zero: the prefetch past the end reads it
   return FX_OK;
 }
 
@@ -322,7 +408,8 @@ int fx_tape_create(const fx_node* nodes, int32_t n_nodes, fx_tape** out) {
   *out = nullptr;
   fx_tape* t = new (std::nothrow) fx_tape;
   if (!t) return fail(FX_E_ARG, "out of host memory");
-  int rc = tape_compile(nodes, n_nodes, &t->prog, &t->info);
+  int rc = tape_compile(nodes, n_nodes, &t->code, &t->info);
+  if (rc == FX_OK) rc = tape_lower(t->code, &t->prog);
   if (rc != FX_OK) {
     delete t;
     return rc;
@@ -336,13 +423,13 @@ void fx_tape_destroy(fx_tape* t) { delete t; }
 int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* slot2, double* imm,
                         int32_t cap) {
   if (!t) return -fail(FX_E_ARG, "NULL tape");
-  const int32_t n = t->prog.n_ins;
+  const int32_t n = t->code.n_ins;
   if (cap > 0 && (!op || !slot || !slot2 || !imm)) return -fail(FX_E_ARG, "NULL output array");
   for (int32_t i = 0; i < n && i < cap; ++i) {
-    op[i] = t->prog.ins[i].op;
-    slot[i] = (uint8_t)(t->prog.ins[i].a & 0xFF);
-    slot2[i] = (uint8_t)(t->prog.ins[i].a >> 8);
-    imm[i] = t->prog.ins[i].kd;
+    op[i] = t->code.ins[i].op;
+    slot[i] = (uint8_t)(t->code.ins[i].a & 0xFF);
+    slot2[i] = (uint8_t)(t->code.ins[i].a >> 8);
+    imm[i] = t->code.ins[i].kd;
   }
   return n;
 }

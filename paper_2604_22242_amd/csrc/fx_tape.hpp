@@ -2,23 +2,32 @@
 //
 // Expressions whose tree is only known at run time cannot be C++ types, so
 // the host compiles the tree into a short accumulator program and the device
-// interprets it per element.  The running value lives in ordinary registers
-// (the accumulator); values needed later (inputs, spilled partial results,
-// nodes used more than once) live in a slot file of at most kTapeMaxSlots
-// entries, and constants travel as immediates.  An instruction combines the
-// accumulator with at most one slot or immediate, so a chain of operators
-// such as exp(0 - abs(a)) costs only its arithmetic.  The program travels
+// interprets it per element.  Two forms of the program exist.
+//
+// The architectural form (tape_code, listed by fx_tape_program): the running
+// value lives in an accumulator; values needed later (inputs, spilled
+// partial results, nodes used more than once) live in at most kTapeMaxSlots
+// slots; an instruction combines the accumulator with at most one slot or
+// immediate, so a chain of operators such as exp(0 - abs(a)) costs only its
+// arithmetic.
+//
+// The device form (tape_prog): the host lowers every architectural
+// instruction into micro-operations whose slot operand is part of the
+// operation code (U_ADD + 3 adds slot 3).  Each case of the device's
+// dispatch names its slot registers statically, so slot values stay in
+// fixed VGPRs and an operand costs nothing beyond the arithmetic that uses
+// it: no register-indexing mode, no moves.  Guard patterns of the form
+// exp(-|a|), sqrt(|a|) and |a| + k are single micro-operations whose
+// absolute value and negation become free source modifiers.  Divisions
+// share one body per slot-file size (the operand is copied in first; the
+// divide itself costs more than ten times the copy).  The program travels
 // inside the kernel argument (or, for batches, in device memory), so every
-// instruction fetch is a wave-uniform scalar load and the dispatch is a
-// uniform branch.  Each lane's slot file is one 16-wide vector value indexed
-// with those uniform slot numbers, which gfx950 serves from VGPRs in indexed
-// mode (s_set_gpr_idx_on) rather than from private memory; lanes are
-// interpreted in passes of 4 (FP32 compute) or 2 (FP64) so the files stay in
-// registers.  TapeExpr<T> has the same interface as a compile-time
-// expression, so the element-wise, full reduction, column-sum and row-sum
-// skeletons (and their single-pass finish) serve tapes unchanged; its
-// eval_tile overload loads every input of all EPT vectors before
-// interpreting them one vector at a time.
+// fetch is a wave-uniform scalar load and the dispatch is a uniform branch
+// tree.  Lanes are interpreted in passes sized so that the slot file holds
+// 64 VGPRs.  TapeExpr<T> has the same interface as a compile-time expression,
+// so the element-wise, full reduction, column-sum and row-sum skeletons (and
+// their single-pass finish) serve tapes unchanged; its eval_tile overload
+// loads every input of all EPT vectors before interpreting them.
 #pragma once
 
 #include <mutex>
@@ -27,9 +36,12 @@
 namespace fx {
 
 constexpr int kTapeMaxIn = 4;
-constexpr int kTapeMaxIns = 128;
+constexpr int kTapeMaxIns = 128;     // architectural instructions
 constexpr int kTapeMaxSlots = 16;
+constexpr int kTapeMaxUops = 320;    // micro-operations of the lowered form
+constexpr int kTapeMaxConsts = 128;  // FP64 immediates of the lowered form
 
+// ---- architectural form (host) ---------------------------------------------
 // acc is the accumulator, y the operand: slot s[a] (suffix S) or the
 // immediate (suffix I).  R-forms put the operand on the left.  The codes are
 // the fx_tape_opcode values of the C interface.
@@ -49,153 +61,175 @@ enum : uint8_t {
 };
 static_assert(A_LD == FX_TI_LD && A_ST == FX_TI_ST && A_ADD_S == FX_TI_ADD_S &&
                   A_RDIV_I == FX_TI_RDIV_I && A_SQRT == FX_TI_SQRT && A_STLD == FX_TI_STLD,
-              "interpreter opcodes follow fx_tape_opcode");
+              "architectural opcodes follow fx_tape_opcode");
 // Input modifiers of an instruction that reads the accumulator, applied in
 // this order before the operation: acc = s[a2] (a load folded into its
 // consumer), acc = |acc|, acc = -acc (abs and neg nodes folded likewise;
 // both are exact).
 constexpr uint16_t kAbsIn = FX_TI_ABS_IN, kNegIn = FX_TI_NEG_IN, kLdIn = FX_TI_LD_IN;
 
-// op and a fill the first 32-bit word together so that a fetch through a
-// device pointer (batches) stays one scalar load: a narrower field would let
-// the compiler shrink it to a 16-bit vector load, whose wait also waits for
-// every input load in flight.
 struct tape_ins {
   uint16_t op, a;  // a: slot index (LD, ST and S-forms) | second slot a2 << 8
-  float kf;        // immediate for FP32 compute
-  double kd;       // immediate for FP64 compute
+  float kf;        // immediate rounded to FP32
+  double kd;       // immediate
 };
 
-// ins[n_ins] is always readable (the array has one spare zero entry): the
-// interpreter fetches instruction pc + 1 while it executes instruction pc.
-struct tape_prog {
+struct tape_code {
   int32_t n_ins, n_in, n_slots, pad;
   tape_ins ins[kTapeMaxIns + 1];
 };
 
-template <class C> __device__ __forceinline__ C tape_imm(const tape_ins& I);
-template <> __device__ __forceinline__ float tape_imm<float>(const tape_ins& I) { return I.kf; }
-template <> __device__ __forceinline__ double tape_imm<double>(const tape_ins& I) { return I.kd; }
+// ---- device form -----------------------------------------------------------
+// Slot families (code = family + slot) and slot-free operations.
+enum : uint8_t {
+  U_LD = 0x00,    // acc = s[k]
+  U_ST = 0x10,    // s[k] = acc
+  U_ADD = 0x20,   // acc = acc + s[k]
+  U_SUB = 0x30,   // acc = acc - s[k]
+  U_RSUB = 0x40,  // acc = s[k] - acc
+  U_MUL = 0x50,   // acc = acc % s[k]
+  U_DIV = 0x60,   // acc = acc / s[k]
+  U_RDIV = 0x70,  // acc = s[k] / acc
+  U_LDI = 0x80,   // acc = imm
+  U_ADDI,         // acc = acc + imm   (also acc - imm, as acc + (-imm): the same IEEE result)
+  U_ADDI_ABS,     // acc = |acc| + imm
+  U_RSUBI,        // acc = imm - acc
+  U_MULI,         // acc = acc % imm
+  U_DIVI,         // acc = acc / imm
+  U_RDIVI,        // acc = imm / acc
+  U_NEG, U_ABS, U_EXP, U_SQRT,
+  U_EXP_NABS,     // acc = exp(-|acc|)
+  U_SQRT_ABS,     // acc = sqrt(|acc|)
+  U_END
+};
 
-// Slot files.  Each is one 16-wide vector value, the width for which the
-// compiler indexes registers in place (narrower vectors get select chains).
-// A program needing at most 8 slots keeps two lanes per file, interleaved
-// (element 2 * slot + lane): half the registers, higher occupancy; every
-// generated tree so far fits.  Otherwise each lane has a file of 16 slots.
-template <class C> struct slot_vec;
-template <> struct slot_vec<float> { typedef float type __attribute__((ext_vector_type(16))); };
-template <> struct slot_vec<double> { typedef double type __attribute__((ext_vector_type(16))); };
-template <class C> using slots_t = typename slot_vec<C>::type;
-constexpr int kTapeSmallSlots = 8;
-// lanes per file, files for L lanes
-template <int S> constexpr int kLanesPerFile = 16 / S;
-template <int S, int L> constexpr int kFiles = (L + kLanesPerFile<S> - 1) / kLanesPerFile<S>;
-#define FX_SLOT(f, j, a) f[(j) / P][(a) * P + (j) % P]
-// Lanes interpreted per pass: every interpreted instruction is one fetch and
-// one dispatch for all of them.
-#ifndef FX_TAPE_PASS_LANES
-#define FX_TAPE_PASS_LANES 8
-#endif
-template <class C> constexpr int kPassLanes = sizeof(C) == 4 ? FX_TAPE_PASS_LANES
-                                                              : (FX_TAPE_PASS_LANES + 1) / 2;
+struct tape_uop {
+  uint8_t op;    // U_*
+  uint8_t ki;    // index of the immediate in tape_prog::kd
+  uint16_t pad;
+  float kf;      // the immediate rounded to FP32 (FP32 compute)
+};
 
-// acc[j] = OP(acc[j], y) for slot and immediate operands (and the reversed
-// forms): each case computes straight into the accumulator so no operand
-// copies survive the branch merge.
-#define FX_TAPE_BIN(NAME, OPK)                                                     \
-  case A_##NAME##_S:                                                              \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], FX_SLOT(s, j, a)); \
-    break;                                                                        \
-  case A_##NAME##_I:                                                              \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j], k); \
-    break;                                                                        \
-  case A_R##NAME##_S:                                                             \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(FX_SLOT(s, j, a), acc[j]); \
-    break;                                                                        \
-  case A_R##NAME##_I:                                                             \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(k, acc[j]); \
-    break;
+// ins[n_ins] is always readable (the array has one spare zero entry): the
+// interpreter fetches micro-operation pc + 1 while it executes pc.
+struct tape_prog {
+  int32_t n_ins, n_in, n_slots, n_consts;
+  double kd[kTapeMaxConsts];  // immediates for FP64 compute
+  tape_uop ins[kTapeMaxUops + 1];
+};
 
-#define FX_TAPE_UN(NAME, OPK)                                                     \
-  case A_##NAME:                                                                  \
-    _Pragma("unroll") for (int j = 0; j < L; ++j) acc[j] = OPK::apply(acc[j]);    \
-    break;
-
-// Interpret `prog` on L lanes whose inputs already sit in slots [0, n_in);
-// the result is left in acc.
-template <class C, int L, int S>
-__device__ __forceinline__ void tape_run(const tape_prog& prog, slots_t<C> (&s)[kFiles<S, L>],
-                                         C (&acc)[L]) {
-  constexpr int P = kLanesPerFile<S>;
-  const int n = prog.n_ins;
-  tape_ins I = prog.ins[0];
-  for (int pc = 0; pc < n; ++pc) {
-    const tape_ins next = prog.ins[pc + 1];
-    const C k = tape_imm<C>(I);
-    const unsigned op = I.op;
-    const unsigned a = I.a & 0xFFu, a2 = I.a >> 8;
-    if (op & (kAbsIn | kNegIn | kLdIn)) {
-      if (op & kLdIn)
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, a2);
-      if (op & kAbsIn)
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_abs::apply(acc[j]);
-      if (op & kNegIn)
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_neg::apply(acc[j]);
-    }
-    switch (op & 0xFFu) {
-      case A_LD:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = FX_SLOT(s, j, a);
-        break;
-      case A_LDI:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = k;
-        break;
-      case A_ST:
-#pragma unroll
-        for (int j = 0; j < L; ++j) FX_SLOT(s, j, a) = acc[j];
-        break;
-      case A_ADD_S:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], FX_SLOT(s, j, a));
-        break;
-      case A_ADD_I:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_add::apply(acc[j], k);
-        break;
-      FX_TAPE_BIN(SUB, op_sub)
-      case A_MUL_S:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], FX_SLOT(s, j, a));
-        break;
-      case A_MUL_I:
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[j] = op_schur::apply(acc[j], k);
-        break;
-      FX_TAPE_BIN(DIV, op_div)
-      FX_TAPE_UN(NEG, op_neg)
-      FX_TAPE_UN(ABS, op_abs)
-      FX_TAPE_UN(EXP, op_exp)
-      FX_TAPE_UN(SQRT, op_sqrt)
-      case A_STLD:
-#pragma unroll
-        for (int j = 0; j < L; ++j) {
-          FX_SLOT(s, j, a) = acc[j];
-          acc[j] = FX_SLOT(s, j, a2);
-        }
-        break;
-      default:
-        break;
-    }
-    I = next;
-  }
+template <class C> __device__ __forceinline__ C tape_imm(const tape_prog& p, const tape_uop& I);
+template <> __device__ __forceinline__ float tape_imm<float>(const tape_prog&, const tape_uop& I) {
+  return I.kf;
+}
+template <> __device__ __forceinline__ double tape_imm<double>(const tape_prog& p, const tape_uop& I) {
+  return p.kd[I.ki];
 }
 
-#undef FX_TAPE_BIN
-#undef FX_TAPE_UN
+// Slot-file sizes the device is compiled for, and the lanes of one pass:
+// the file holds 64 VGPRs (16 slots: half the lanes).
+constexpr int kTapeSmallSlots = 8;
+template <class C, int S> constexpr int kPassLanes = (64 * 4) / (S * (int)sizeof(C));
+
+// One case per slot of a family; BODY(K) is the statement for slot K.
+#define FX_SLOT_CASES8(FAM, BODY)                                                    \
+  case (FAM) + 0: BODY(0) case (FAM) + 1: BODY(1) case (FAM) + 2: BODY(2)             \
+  case (FAM) + 3: BODY(3) case (FAM) + 4: BODY(4) case (FAM) + 5: BODY(5)             \
+  case (FAM) + 6: BODY(6) case (FAM) + 7: BODY(7)
+#define FX_SLOT_CASES16(FAM, BODY)                                                   \
+  FX_SLOT_CASES8(FAM, BODY)                                                          \
+  case (FAM) + 8: BODY(8) case (FAM) + 9: BODY(9) case (FAM) + 10: BODY(10)           \
+  case (FAM) + 11: BODY(11) case (FAM) + 12: BODY(12) case (FAM) + 13: BODY(13)       \
+  case (FAM) + 14: BODY(14) case (FAM) + 15: BODY(15)
+
+#define FX_LANES(STMT) _Pragma("unroll") for (int j = 0; j < L; ++j) { STMT; }
+#define FX_U_LD(K) FX_LANES(acc[j] = s[K][j]) break;
+#define FX_U_ST(K) FX_LANES(s[K][j] = acc[j]) break;
+#define FX_U_ADD(K) FX_LANES(acc[j] = acc[j] + s[K][j]) break;
+#define FX_U_SUB(K) FX_LANES(acc[j] = acc[j] - s[K][j]) break;
+#define FX_U_RSUB(K) FX_LANES(acc[j] = s[K][j] - acc[j]) break;
+#define FX_U_MUL(K) FX_LANES(acc[j] = acc[j] * s[K][j]) break;
+#define FX_U_DIV(K) FX_LANES(y[j] = s[K][j]) goto div_y;
+#define FX_U_RDIV(K) FX_LANES(y[j] = s[K][j]) goto rdiv_y;
+
+// The whole dispatch for one slot-file size (SC: FX_SLOT_CASES8 or 16).
+#define FX_TAPE_SWITCH(SC)                                                            \
+  switch (I.op) {                                                                     \
+    SC(U_LD, FX_U_LD)                                                                 \
+    SC(U_ST, FX_U_ST)                                                                 \
+    SC(U_ADD, FX_U_ADD)                                                               \
+    SC(U_SUB, FX_U_SUB)                                                               \
+    SC(U_RSUB, FX_U_RSUB)                                                             \
+    SC(U_MUL, FX_U_MUL)                                                               \
+    SC(U_DIV, FX_U_DIV)                                                               \
+    SC(U_RDIV, FX_U_RDIV)                                                             \
+    case U_LDI: FX_LANES(acc[j] = k) break;                                           \
+    case U_ADDI: FX_LANES(acc[j] = acc[j] + k) break;                                 \
+    case U_ADDI_ABS: FX_LANES(acc[j] = op_abs::apply(acc[j]) + k) break;              \
+    case U_RSUBI: FX_LANES(acc[j] = k - acc[j]) break;                                \
+    case U_MULI: FX_LANES(acc[j] = acc[j] * k) break;                                 \
+    case U_DIVI: FX_LANES(y[j] = k)                                                   \
+    div_y: FX_LANES(acc[j] = acc[j] / y[j]) break;                                    \
+    case U_RDIVI: FX_LANES(y[j] = k)                                                  \
+    rdiv_y: FX_LANES(acc[j] = y[j] / acc[j]) break;                                   \
+    case U_NEG: FX_LANES(acc[j] = -acc[j]) break;                                     \
+    case U_ABS: FX_LANES(acc[j] = op_abs::apply(acc[j])) break;                       \
+    case U_EXP: FX_LANES(acc[j] = op_exp::apply(acc[j])) break;                       \
+    case U_SQRT: FX_LANES(acc[j] = op_sqrt::apply(acc[j])) break;                     \
+    case U_EXP_NABS: FX_LANES(acc[j] = op_exp::apply(-op_abs::apply(acc[j]))) break;  \
+    case U_SQRT_ABS: FX_LANES(acc[j] = op_sqrt::apply(op_abs::apply(acc[j]))) break;  \
+    default: break;                                                                   \
+  }
+
+// Interpret `prog` on L lanes whose inputs already sit in slots [0, n_in);
+// the result is left in acc.  Each micro-operation is one IEEE operation (or
+// library function) per lane, exactly as in the architectural form, so the
+// lowering changes no result bit.  One function per slot-file size (each
+// has its own divide labels).
+#define FX_TAPE_RUN(NAME, S, SC)                                                      \
+  template <class C, int L>                                                           \
+  __device__ __forceinline__ void NAME(const tape_prog& prog, C (&s)[S][L], C (&acc)[L]) { \
+    const int n = prog.n_ins;                                                         \
+    tape_uop I = prog.ins[0];                                                         \
+    for (int pc = 0; pc < n; ++pc) {                                                  \
+      const tape_uop next = prog.ins[pc + 1];                                         \
+      const C k = tape_imm<C>(prog, I);                                               \
+      C y[L];                                                                         \
+      FX_TAPE_SWITCH(SC)                                                              \
+      I = next;                                                                       \
+    }                                                                                 \
+  }
+FX_TAPE_RUN(tape_run8, 8, FX_SLOT_CASES8)
+FX_TAPE_RUN(tape_run16, 16, FX_SLOT_CASES16)
+#undef FX_TAPE_RUN
+
+template <class C, int L, int S>
+__device__ __forceinline__ void tape_run(const tape_prog& prog, C (&s)[S][L], C (&acc)[L]) {
+  static_assert(S == 8 || S == 16, "slot files of 8 or 16");
+  if constexpr (S == 8) tape_run8<C, L>(prog, s, acc);
+  else tape_run16<C, L>(prog, s, acc);
+}
+
+#undef FX_TAPE_SWITCH
+#undef FX_U_LD
+#undef FX_U_ST
+#undef FX_U_ADD
+#undef FX_U_SUB
+#undef FX_U_RSUB
+#undef FX_U_MUL
+#undef FX_U_DIV
+#undef FX_U_RDIV
+#undef FX_LANES
+#undef FX_SLOT_CASES8
+#undef FX_SLOT_CASES16
+
+// Lanes of an input the program does not read: unspecified values, no code.
+template <class C, int N> __device__ __forceinline__ lanes<C, N> unset_lanes() {
+  lanes<C, N> r;
+#pragma unroll
+  for (int j = 0; j < N; ++j) r.v[j] = __builtin_nondeterministic_value(r.v[j]);
+  return r;
+}
 
 // BYREF = false: the program is held by value (it travels in the kernel
 // argument); BYREF = true: it is read through a pointer into device memory
@@ -213,25 +247,26 @@ template <class T, bool BYREF = false, int SLOTS = kTapeSmallSlots> struct TapeE
   }
 
   // Values of N lanes whose inputs are in[q].v[0..N): passes of G lanes.
+  // Slots past the inputs start with unspecified values (every program
+  // stores a slot before it reads it), which costs no instruction.
   template <int N>
   __device__ __forceinline__ lanes<ct, N> interpret(const lanes<ct, N> (&in)[kTapeMaxIn]) const {
-    constexpr int G = N < kPassLanes<ct> ? N : kPassLanes<ct>;
+    constexpr int G = N < kPassLanes<ct, SLOTS> ? N : kPassLanes<ct, SLOTS>;
     const tape_prog& pr = P();
     lanes<ct, N> r;
 #pragma unroll
     for (int g = 0; g < N; g += G) {
-      constexpr int P = kLanesPerFile<SLOTS>;
-      slots_t<ct> s[kFiles<SLOTS, G>];
+      ct s[SLOTS][G];
 #pragma unroll
-      for (int f = 0; f < kFiles<SLOTS, G>; ++f) s[f] = slots_t<ct>{};
+      for (int j = 0; j < G; ++j) {
 #pragma unroll
-      for (int j = 0; j < G; ++j)
+        for (int a = 0; a < kTapeMaxIn; ++a) s[a][j] = in[a].v[g + j];
 #pragma unroll
-        for (int q = 0; q < kTapeMaxIn; ++q)
-          if (q < pr.n_in) FX_SLOT(s, j, q) = in[q].v[g + j];
+        for (int a = kTapeMaxIn; a < SLOTS; ++a) s[a][j] = __builtin_nondeterministic_value(s[a][j]);
+      }
       ct acc[G];
 #pragma unroll
-      for (int j = 0; j < G; ++j) acc[j] = ct(0);
+      for (int j = 0; j < G; ++j) acc[j] = __builtin_nondeterministic_value(acc[j]);
       tape_run<ct, G, SLOTS>(pr, s, acc);
 #pragma unroll
       for (int j = 0; j < G; ++j) r.v[g + j] = acc[j];
@@ -251,7 +286,7 @@ template <class T, bool BYREF = false, int SLOTS = kTapeSmallSlots> struct TapeE
     const int n_in = P().n_in;
 #pragma unroll
     for (int q = 0; q < kTapeMaxIn; ++q)
-      if (q < n_in) in[q] = load_lanes<N, NT>(p[q], i);
+      in[q] = q < n_in ? load_lanes<N, NT>(p[q], i) : unset_lanes<ct, N>();
     return interpret<N>(in);
   }
   void collect(leaf_info& li) const {
@@ -268,9 +303,9 @@ __device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF, SLOTS>& e, in
   const int n_in = e.P().n_in;
 #pragma unroll
   for (int q = 0; q < kTapeMaxIn; ++q)
-    if (q < n_in)
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) in[k][q] = load_lanes<N, kNT>(e.p[q], base + k * stride);
+    for (int k = 0; k < EPT; ++k)
+      in[k][q] = q < n_in ? load_lanes<N, kNT>(e.p[q], base + k * stride) : unset_lanes<C, N>();
   // the EPT vectors are interpreted together, in passes of kPassLanes lanes
   lanes<C, N * EPT> flat[kTapeMaxIn];
 #pragma unroll
@@ -331,9 +366,11 @@ int tape_eval_impl(const tape_prog& prog, const void* const* inputs, fx_shape s,
     return tape_eval_impl<T, kTapeMaxSlots>(prog, inputs, s, kind, out, ws, ws_bytes, cfg, st);  \
   }
 
-// Host: compile a node list (children first, root last) into a program.
-// Returns FX_OK or an fx_status with fx_last_error set.
-int tape_compile(const fx_node* nodes, int32_t n_nodes, tape_prog* prog, fx_tape_info* info);
+// Host: compile a node list (children first, root last) into the
+// architectural program, and lower that into the device program.  Return
+// FX_OK or an fx_status with fx_last_error set.
+int tape_compile(const fx_node* nodes, int32_t n_nodes, tape_code* code, fx_tape_info* info);
+int tape_lower(const tape_code& code, tape_prog* prog);
 
 }  // namespace fx
 
@@ -341,7 +378,8 @@ int tape_compile(const fx_node* nodes, int32_t n_nodes, tape_prog* prog, fx_tape
 // leave the launch configuration to the library take the model's choice;
 // the last choice is cached (one key: dtype, shape, kind) under `mu`.
 struct fx_tape {
-  fx::tape_prog prog;
+  fx::tape_code code;  // architectural form (fx_tape_program)
+  fx::tape_prog prog;  // device form
   fx_tape_info info;
   const fx_model* model = nullptr;
   mutable std::mutex mu;
