@@ -35,6 +35,45 @@ struct batch_tile {
   uint32_t item, index;
 };
 
+// The batch reads its item pointers from device memory, so the compiler
+// cannot tell that they point to global memory and would use flat
+// instructions, whose completion the scalar instruction fetches of the
+// interpreter then also wait for.  These helpers access them through the
+// global address space.
+#define FX_GLOBAL __attribute__((address_space(1)))
+template <int N, class T>
+__device__ __forceinline__ lanes<ct_t<T>, N> gload_lanes(const T* p, int64_t i) {
+  constexpr int BYTES = N * (int)sizeof(T);
+  static_assert(BYTES <= 16, "one load per vector");
+  using R = typename raw<BYTES>::type;
+  const FX_GLOBAL R* q = (const FX_GLOBAL R*)(p + i);
+  const R r = kNT ? __builtin_nontemporal_load(q) : *q;
+  T s[N];
+  __builtin_memcpy(s, &r, sizeof(R));
+  lanes<ct_t<T>, N> out;
+#pragma unroll
+  for (int j = 0; j < N; ++j) out.v[j] = static_cast<ct_t<T>>(s[j]);
+  return out;
+}
+template <class T> __device__ __forceinline__ ct_t<T> gload(const T* p, int64_t i) {
+  return static_cast<ct_t<T>>(*(const FX_GLOBAL T*)(p + i));
+}
+template <int N, class T>
+__device__ __forceinline__ void gstore_lanes(T* p, int64_t i, const lanes<ct_t<T>, N>& x) {
+  using R = typename raw<N * (int)sizeof(T)>::type;
+  T s[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) s[j] = static_cast<T>(x.v[j]);
+  R r;
+  __builtin_memcpy(&r, s, sizeof(R));
+  FX_GLOBAL R* q = (FX_GLOBAL R*)(p + i);
+  if (kNTS) __builtin_nontemporal_store(r, q);
+  else *q = r;
+}
+template <class T> __device__ __forceinline__ void gstore(T* p, int64_t i, ct_t<T> v) {
+  *(FX_GLOBAL T*)(p + i) = static_cast<T>(v);
+}
+
 // Inputs of EPT vectors at base + k * stride, of which only the elements
 // below `end` exist (the last pass of an item): whole vectors load as
 // vectors, the vector that straddles `end` element by element.
@@ -49,13 +88,13 @@ __device__ __forceinline__ void batch_load_tail(const X& x, int n_in, int64_t ba
 #pragma unroll
     for (int q = 0; q < kTapeMaxIn; ++q) {
       if (q < n_in && e + N <= end) {
-        in[k][q] = load_lanes<N, kNT>(x.p[q], e);
+        in[k][q] = gload_lanes<N>(x.p[q], e);
       } else {
         in[k][q] = unset_lanes<C, N>();
         if (q < n_in)
 #pragma unroll
           for (int j = 0; j < N; ++j)
-            if (e + j < end) in[k][q].v[j] = static_cast<C>(x.p[q][e + j]);
+            if (e + j < end) in[k][q].v[j] = gload(x.p[q], e + j);
       }
     }
   }
@@ -94,7 +133,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
     T* z = static_cast<T*>(d.out);
     const int64_t i0 = (int64_t)tl.index * tile_elems;
     const int64_t i1 = min(d.n, i0 + tile_elems);
-    lane_accum<C, N> acc;
+    // one compensated chain per thread (the interpreter between two passes
+    // leaves the chain's dependent additions ample time; a chain per vector
+    // lane would cost registers, and with them occupancy)
+    accum<C> acc;
     for (int64_t e0 = i0; e0 < i1; e0 += pass) {
       const int64_t base = e0 + (int64_t)threadIdx.x * N;
       const bool whole = e0 + pass <= i1;  // uniform
@@ -104,7 +146,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
         for (int q = 0; q < kTapeMaxIn; ++q)
 #pragma unroll
           for (int k = 0; k < EPT; ++k)
-            in[k][q] = q < n_in ? load_lanes<N, kNT>(x.p[q], base + k * stride) : unset_lanes<C, N>();
+            in[k][q] = q < n_in ? gload_lanes<N>(x.p[q], base + k * stride) : unset_lanes<C, N>();
       } else {
         batch_load_tail<N, EPT>(x, n_in, base, stride, i1, in);
       }
@@ -123,8 +165,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
           lanes<C, N> v;
 #pragma unroll
           for (int j = 0; j < N; ++j) v.v[j] = r.v[k * N + j];
-          if (ew) store_lanes<N, kNTS>(z, base + k * stride, v);
-          else add_lanes<map_id>(acc, v);
+          if (ew) {
+            gstore_lanes<N>(z, base + k * stride, v);
+          } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc.add(v.v[j]);
+          }
         }
       } else {
 #pragma unroll
@@ -133,8 +179,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
 #pragma unroll
           for (int j = 0; j < N; ++j) {
             if (e + j < i1) {
-              if (ew) z[e + j] = static_cast<T>(r.v[k * N + j]);
-              else acc.a[j].add(r.v[k * N + j]);
+              if (ew) gstore(z, e + j, r.v[k * N + j]);
+              else acc.add(r.v[k * N + j]);
             }
           }
         }
@@ -143,13 +189,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
     if (!ew) {
       const double s = block_sum<double>(acc.value(), lds);
       if (d.n_tiles == 1) {
-        if (threadIdx.x == 0) *static_cast<double*>(d.out) = s;
+        if (threadIdx.x == 0) *(FX_GLOBAL double*)d.out = s;
       } else {
         const int64_t pt = d.first_tile + tl.index;  // partials in tile order per item
         if (threadIdx.x == 0) publish(partials + pt, s);
         if (take_last_ticket(counters + tl.item, d.n_tiles)) {
           if (threadIdx.x == 0) {
-            *static_cast<double*>(d.out) = sum_strided<double>(partials + d.first_tile, 1, d.n_tiles);
+            *(FX_GLOBAL double*)d.out = sum_strided<double>(partials + d.first_tile, 1, d.n_tiles);
             reset_counter(counters + tl.item);
           }
         }
@@ -227,6 +273,25 @@ template <class F> static int batch_dispatch(fx_dtype dt, int vec, int ept, F&& 
   });
 }
 
+// Blocks of the batch kernel that one CU holds at once (the persistent grid
+// is that many per CU: more would only wait for the queue to drain).
+static int batch_resident_blocks(fx_dtype dt, int vec, int ept, bool small_slots, int block,
+                                 int* out) {
+  return batch_dispatch(dt, vec, ept, [&](auto tg, auto Nc, auto Ec) {
+    using T = typename decltype(tg)::type;
+    constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
+    int nb = 0;
+    const hipError_t e =
+        small_slots ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &nb, k_batch<T, N, EPT, kTapeSmallSlots>, block, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                          &nb, k_batch<T, N, EPT, kTapeMaxSlots>, block, 0);
+    if (int rc = hip_check(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")) return rc;
+    *out = nb > 0 ? nb : 1;
+    return (int)FX_OK;
+  });
+}
+
 static int batch_run(fx_batch* b, hipStream_t st) {
   const fx_batch_info& I = b->info;
   if (I.n_tiles == 0) return FX_OK;
@@ -292,7 +357,7 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     I.ept = c.ept ? c.ept : std::max(1, std::min(2, pass_lanes / b->vec));
   }
   const int64_t pass = (int64_t)I.block * I.ept * b->vec;
-  const int64_t want = tile_elems ? tile_elems : 16384;
+  const int64_t want = tile_elems ? tile_elems : 32768;
   I.tile_elems = ceil_div(want, pass) * pass;
   // tile table
   std::vector<batch_desc> descs(count);
@@ -337,7 +402,14 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     for (size_t q = 0; q < order.size(); ++q) sorted[q] = tiles[order[q]];
     tiles.swap(sorted);
   }
-  const int64_t grid_default = (int64_t)device_cus() * 8;
+  int resident = 1;
+  if (!c.split) {
+    if (int rc = batch_resident_blocks(dt, b->vec, I.ept, b->small_slots, I.block, &resident)) {
+      delete b;
+      return rc;
+    }
+  }
+  const int64_t grid_default = (int64_t)device_cus() * resident;
   I.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(c.split ? c.split : grid_default,
                                                           std::max<int64_t>(1, I.n_tiles)));
   // workspaces for launching the items one by one (default configuration)

@@ -149,8 +149,8 @@ template <class C, int S> constexpr int kPassLanes = (64 * 4) / (S * (int)sizeof
 #define FX_U_SUB(K) FX_LANES(acc[j] = acc[j] - s[K][j]) break;
 #define FX_U_RSUB(K) FX_LANES(acc[j] = s[K][j] - acc[j]) break;
 #define FX_U_MUL(K) FX_LANES(acc[j] = acc[j] * s[K][j]) break;
-#define FX_U_DIV(K) FX_LANES(y[j] = s[K][j]) goto div_y;
-#define FX_U_RDIV(K) FX_LANES(y[j] = s[K][j]) goto rdiv_y;
+#define FX_U_DIV(K) FX_LANES(acc[j] = acc[j] / s[K][j]) break;
+#define FX_U_RDIV(K) FX_LANES(acc[j] = s[K][j] / acc[j]) break;
 
 // The whole dispatch for one slot-file size (SC: FX_SLOT_CASES8 or 16).
 #define FX_TAPE_SWITCH(SC)                                                            \
@@ -168,10 +168,8 @@ template <class C, int S> constexpr int kPassLanes = (64 * 4) / (S * (int)sizeof
     case U_ADDI_ABS: FX_LANES(acc[j] = op_abs::apply(acc[j]) + k) break;              \
     case U_RSUBI: FX_LANES(acc[j] = k - acc[j]) break;                                \
     case U_MULI: FX_LANES(acc[j] = acc[j] * k) break;                                 \
-    case U_DIVI: FX_LANES(y[j] = k)                                                   \
-    div_y: FX_LANES(acc[j] = acc[j] / y[j]) break;                                    \
-    case U_RDIVI: FX_LANES(y[j] = k)                                                  \
-    rdiv_y: FX_LANES(acc[j] = y[j] / acc[j]) break;                                   \
+    case U_DIVI: FX_LANES(acc[j] = acc[j] / k) break;                                 \
+    case U_RDIVI: FX_LANES(acc[j] = k / acc[j]) break;                                \
     case U_NEG: FX_LANES(acc[j] = -acc[j]) break;                                     \
     case U_ABS: FX_LANES(acc[j] = op_abs::apply(acc[j])) break;                       \
     case U_EXP: FX_LANES(acc[j] = op_exp::apply(acc[j])) break;                       \
@@ -194,7 +192,6 @@ template <class C, int S> constexpr int kPassLanes = (64 * 4) / (S * (int)sizeof
     for (int pc = 0; pc < n; ++pc) {                                                  \
       const tape_uop next = prog.ins[pc + 1];                                         \
       const C k = tape_imm<C>(prog, I);                                               \
-      C y[L];                                                                         \
       FX_TAPE_SWITCH(SC)                                                              \
       I = next;                                                                       \
     }                                                                                 \
