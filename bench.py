@@ -503,6 +503,41 @@ def measured_traffic(kernel_tag="k_ew[c2,f32"):
     return None
 
 
+VALU_PROFILE = os.path.join(ROOT, "profiles", "c2_8192_fused_valu.md")
+SIMDS, CLOCK_HZ = 1024, 2.4e9  # MI355X: 256 CUs x 4 SIMDs, peak engine clock
+
+
+def measured_valu():
+    """{dtype: {result: VALU issue quad-cycles per launch}} from the committed
+    rocprofv3 SQ_ACTIVE_INST_VALU summary, or None if there is none or the
+    kernel sources have changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(VALU_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+    m = re.search(r"Kernel source hash[^:]*: ([0-9a-f]{16})", text)
+    j = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m or m.group(1) != h or not j:
+        return None
+    return json.loads(j.group(1))
+
+
+def valu_roofline(counts, dt, live_ms):
+    """VALU-time bound of each result (every SIMD issuing VALU work every
+    cycle: 4 cycles per quad-cycle counted) and the live time's fraction of
+    it."""
+    if not counts or dt not in counts:
+        return {}
+    out = {}
+    for r, q in counts[dt].items():
+        bound_ms = q * 4 / (SIMDS * CLOCK_HZ) * 1e3
+        out[r] = {"valu_bound_ms": round(bound_ms, 5), "valu_frac": round(bound_ms / live_ms[r], 3)}
+    return out
+
+
 def cpu_baseline(cols_sample=COLS, min_seconds=10.0, threads=None):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
     same three results over the first `cols_sample` columns, repeated until
@@ -683,8 +718,14 @@ def main():
         _, bms = time_steps(torch, wb.fused, a.steps, a.warmup, stream)
         _, bums = time_steps(torch, wb.unfused, a.steps, a.warmup, stream)
         detail["bf16_fused"] = {r: {"ms": round(bms[r], 5),
-                                    "GB/s": round(wb.bytes[r] / (bms[r] * 1e-3) / 1e9, 1)}
+                                    "GB/s": round(wb.bytes[r] / (bms[r] * 1e-3) / 1e9, 1),
+                                    "hbm_frac": round(wb.bytes[r] / (bms[r] * 1e-3) / 1e9
+                                                      / PEAK_HBM_GBS, 3)}
                                 for r in RESULTS}
+        # BF16 storage halves the bytes but not the arithmetic: the VALU-time
+        # bound from the committed instruction counts, against the live time
+        for r, v in valu_roofline(measured_valu(), "bf16", bms).items():
+            detail["bf16_fused"][r].update(v)
         detail["bf16_speedup_vs_unfused"] = {r: round(bums[r] / bms[r], 3) for r in RESULTS}
         detail["bf16_speedup_vs_fp32_storage"] = {r: round(ms[r] / bms[r], 3) for r in RESULTS}
         del wb
