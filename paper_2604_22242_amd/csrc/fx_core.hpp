@@ -96,12 +96,16 @@ __device__ __forceinline__ void store_lanes(T* __restrict__ p, int64_t i, const 
 }
 
 // ---------------------------------------------------------------------------
-// Per-thread accumulation.  Floating point: Kahan's compensated sum in the
-// compute type, one compensated add per element (the running sum s and the
-// negated low-order part c that s has lost; the sum is s - c), handed upward
-// in FP64.  Its error is at most about 2u times the sum of the magnitudes of
-// the thread's terms, however many terms the thread adds.  Integers: plain
-// u64, exact.
+// Per-thread accumulation.  Floating point: compensated summation in the
+// compute type with Neumaier's refinement of Kahan's method, one compensated
+// add per element: the running sum s, and c, the sum of the exact rounding
+// errors of the additions into s; the thread's sum is s + c, handed upward in
+// FP64.  Each error is taken with Knuth's branch-free TwoSum (six additions,
+// exact whichever operand is larger), which on gfx950 avoids the compare and
+// selects of the magnitude test, and the hazard waits between them.  The
+// error of the sum is about u |sum| plus a term of order n u^2 times the sum
+// of the magnitudes of the thread's terms, so cancellation costs no accuracy.
+// Integers: plain u64, exact.
 
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
@@ -110,14 +114,15 @@ template <class C> struct accum {
   C s = 0, c = 0;
   __device__ __forceinline__ void add(C t) {
 #pragma clang fp contract(off)
-    const C y = t - c;
-    const C u = s + y;
-    c = (u - s) - y;
+    const C u = s + t;
+    const C tv = u - s;          // the part of t that reached u
+    const C sv = u - tv;         // the part of s that reached u
+    c += (s - sv) + (t - tv);    // what u lost of each, exactly
     s = u;
   }
   // an infinite or NaN running sum is the sum (its compensation is NaN)
   __device__ __forceinline__ double value() const {
-    return __builtin_isfinite(s) ? (double)s - (double)c : (double)s;
+    return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
   }
 };
 template <> struct accum<uint32_t> {
@@ -240,7 +245,7 @@ constexpr int default_block(int kind, int elem) {
   return kind == 0 ? 512
        : kind == FX_R_COLSUM ? (elem >= 4 ? 512 : 256)
        : kind == FX_R_ROWSUM ? (elem >= 4 ? 256 : 64)
-       : 256;  // full reductions
+       : elem >= 4 ? 256 : 512;  // full reductions
 }
 constexpr int default_ept(int kind, int elem) {
   return kind == 0 ? 1 : kind == FX_R_COLSUM ? (elem >= 4 ? 2 : 1) : 2;

@@ -8,7 +8,7 @@
 // ahead-of-time template instantiation and the tape interpreter.  The
 // generated kernel does the reads and writes of a compile-time one with no
 // interpreter cost; its skeletons take the same per-thread element
-// assignment, Kahan per-thread sums in the compute type, wave64 + LDS
+// assignment, compensated per-thread sums in the compute type, wave64 + LDS
 // block sums in FP64 and single-pass ticket finish as the compile-time
 // skeletons, with the library's default block size and EPT of the kind and
 // storage type written into the text.

@@ -11,7 +11,7 @@
 //   fx_eval<N>(FX_ARGS, raw, r)   the expression on those N elements
 //   fx_at(FX_ARGS, i)             the expression at element i
 // The skeletons are those of the compile-time kernels: EPT vectors per input
-// loaded before any arithmetic, Kahan per-thread sums in the compute type,
+// loaded before any arithmetic, compensated per-thread sums in the compute type,
 // FP64 wave64 + LDS block sums and the single-pass agent-scope ticket finish.
 #pragma once
 
@@ -93,8 +93,10 @@ extern "C" __global__ __launch_bounds__(FX_BLOCK) void fx_rtc_ew(FX_PARAMS, st_t
 }
 )";
 
-// Sums: Kahan's compensated per-thread sum in the compute type, one
-// compensated add per element, handed upward in FP64; the block sum is a
+// Sums: compensated per-thread sums in the compute type (Neumaier's
+// refinement of Kahan's method: c collects the exact rounding error of every
+// addition into s, taken with Knuth's TwoSum), one compensated add per
+// element, handed upward in FP64; the block sum is a
 // wave64 butterfly and then the waves' results in order; partials are
 // published with agent-scope stores and the block that draws the last ticket
 // of an agent-scope counter adds them in index order after one acquire, then
@@ -105,13 +107,13 @@ struct fx_acc {
 };
 __device__ __forceinline__ void fx_add(fx_acc& a, ct_t t) {
 #pragma clang fp contract(off)
-  const ct_t y = t - a.c;
-  const ct_t u = a.s + y;
-  a.c = (u - a.s) - y;
+  const ct_t u = a.s + t;
+  const ct_t tv = u - a.s, sv = u - tv;  // TwoSum: the exact error of a.s + t
+  a.c += (a.s - sv) + (t - tv);
   a.s = u;
 }
 __device__ __forceinline__ double fx_value(const fx_acc& a) {
-  return __builtin_isfinite(a.s) ? (double)a.s - (double)a.c : (double)a.s;
+  return __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
 }
 // one chain per vector lane, added in FP64 in lane order
 template <int N> __device__ __forceinline__ double fx_lanes_value(const fx_acc (&a)[N]) {
