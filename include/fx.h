@@ -70,7 +70,9 @@ typedef enum {
 /* Launch configuration; 0 in a field means "library default".
  *   block:     threads per block, a multiple of 64 in [64, 512]
  *   ept:       independent vector loads per input per thread, 1/2/4/8
- *   vec_bytes: bytes per vector load: 4, 8 or 16 (at least one element)
+ *              (tapes: 1/2/4)
+ *   vec_bytes: bytes per vector load: one element or 16; tapes over types
+ *              of at most 4 bytes also take 8.  Other values: FX_E_UNSUPPORTED
  *   split:     element-wise and full reductions: number of blocks (grid);
  *              column sums: blocks per column; row sums: column chunks. */
 typedef struct { int32_t block, ept, vec_bytes, split; } fx_launch;
@@ -364,7 +366,9 @@ int32_t fx_tape_program(const fx_tape* t, uint16_t* op, uint8_t* slot, uint8_t* 
  * when there are at least as many columns as CUs; row sums 256 threads,
  * EPT 2, one row per thread, 64 column chunks.  The split default applies
  * only when all of cfg is 0 (or cfg is NULL); then a model attached with
- * fx_tape_set_model chooses instead. */
+ * fx_tape_set_model chooses instead.  Tapes are compiled for EPT 1, 2 and 4
+ * and for vectors of one element, 8 or 16 bytes: other explicit values give
+ * FX_E_UNSUPPORTED. */
 int fx_tape_eval(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32_t n_inputs,
                  fx_shape shape, int kind, void* out, void* ws, size_t ws_bytes,
                  const fx_launch* cfg, void* stream);
@@ -529,11 +533,11 @@ int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* inputs, int32
 
 /* The exhaustive autotuner's configuration grid for a tape of result kind
  * `kind` (0 or FX_R_*) and storage dtype dt: block {64, 128, 256, 512} x EPT
- * {1, 2} x vector {one element, 16 bytes} x four split values of the kind
- * (element-wise 0, 2, 8, 32 blocks per CU; accu / norm 1, 2, 4, 8 blocks per
- * CU; column sums 0, 1, 4, 16 chunks per column; row sums 0, 16, 64, 256
- * column chunks; 0 = the library's choice), then the default (all 0).
- * Writes the 65 configurations to out[0..cap) and returns their count; with
+ * {1, 2, 4} x vector {one element, 8 bytes, 16 bytes} x four split values of
+ * the kind (element-wise 0, 2, 8, 32 blocks per CU; accu / norm 1, 2, 4, 8
+ * blocks per CU; column sums 0, 1, 4, 16 chunks per column; row sums 0, 16,
+ * 64, 256 column chunks; 0 = the library's choice), then the default (all 0).
+ * Writes the 145 configurations to out[0..cap) and returns their count; with
  * out NULL or cap too small, only the count.  Negative fx_status on a bad
  * kind or dtype. */
 int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t cap);
@@ -622,7 +626,9 @@ void fx_model_destroy(fx_model* m);
  * shape `shape` and result kind `kind` (0 or FX_R_ACCU / COLSUM / ROWSUM /
  * NORM), in training order: 8 operator counts (add, sub, schur, div, neg,
  * abs, exp, sqrt); constants, depth, instructions, slots, inputs; 1 for
- * 2-byte storage; log2 of size, rows and columns; the kind one-hot
+ * 2-byte storage; log2 of size, rows and columns (those of an n x 1 shape
+ * for element-wise results and full reductions, which see the data as one
+ * flat vector); the kind one-hot
  * (element-wise, accu, column sums, row sums, norm); bytes per element
  * (inputs, plus the output if element-wise); div + exp + sqrt count; log2
  * of the bytes moved.  Writes them to out[0..cap) and returns 25 (only the
@@ -639,7 +645,7 @@ int32_t fx_tape_features(const fx_tape* t, fx_dtype dt, fx_shape shape, int kind
 int fx_model_load(const char* path, fx_model** out);
 
 /* The launch configuration the model picks for one feature row: its four
- * heads (block 4, EPT 2, vector 2, split 4 classes) mapped onto the
+ * heads (block 4, EPT 3, vector 3, split 4 classes) mapped onto the
  * autotuner's grid for `kind` and dt (fx_tune_grid), on the host. */
 int fx_model_predict(const fx_model* m, const float* features, int kind, fx_dtype dt,
                      fx_launch* out);

@@ -708,7 +708,7 @@ def fx_tape_features(tape: Tape, dt, shape, kind=0) -> list:
 
 
 def fx_tune_grid(kind, dt) -> list:
-    """The autotuner's configuration grid (65 tuples, the default last)."""
+    """The autotuner's configuration grid (145 tuples, the default last)."""
     n = lib().fx_tune_grid(kind, dt, None, 0)
     if n < 0:
         check(-n)

@@ -335,12 +335,24 @@ template <int MAX = 8, class F> inline int with_ept(int ept, F&& f) {
   return fail(FX_E_UNSUPPORTED, "ept %d not compiled for this expression (max %d)", ept, MAX);
 }
 
-// Vector width in elements: one element (any alignment) or 16 bytes.
-template <class T, class F> inline int with_vec(int vec_elems, F&& f) {
+// Expression types compiled for 8-byte vectors as well (the run-time tape,
+// whose launch the autotuner searches); the others take one element (any
+// alignment) or 16 bytes.
+template <class E> struct vec8_compiled { static constexpr bool value = false; };
+template <class E> struct vec8_compiled<Fused<E>> { static constexpr bool value = vec8_compiled<E>::value; };
+template <class E> constexpr bool vec8_compiled_v = vec8_compiled<E>::value;
+
+// Vector width in elements: one element, 8 bytes (where compiled) or 16 bytes.
+template <class T, class E = void, class F> inline int with_vec(int vec_elems, F&& f) {
   constexpr int W = 16 / (int)sizeof(T);
+  constexpr bool V8 = W >= 4 && vec8_compiled_v<E>;
   if (vec_elems == 1) return f(ic<1>{});
   if (vec_elems == W) return f(ic<W>{});
-  return fail(FX_E_UNSUPPORTED, "vector of %d elements not compiled (1 or %d)", vec_elems, W);
+  if constexpr (V8) {
+    if (vec_elems == W / 2) return f(ic<W / 2>{});
+  }
+  return fail(FX_E_UNSUPPORTED, "vector of %d elements not compiled (1 or %d%s)", vec_elems, W,
+              V8 ? " or half of it" : "");
 }
 
 // Resolve a configuration for `n_elems` elements of storage size `elem` with
@@ -396,7 +408,7 @@ int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
   launch L = resolve(0, sizeof(T), rows, cols, cfg, li.aligned(16));
   clamp_ept<E>(L, cfg);
   const int vec = L.vec_bytes / (int)sizeof(T);
-  return with_vec<T>(vec, [&](auto Nc) {
+  return with_vec<T, E>(vec, [&](auto Nc) {
     return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_ew<E, T, N, EPT>), dim3(L.split), dim3(L.block), 0, st, e, z, n);
@@ -440,7 +452,7 @@ int reduce_full_direct(const E& e, void* out, void* ws, size_t ws_bytes, const f
   ws_layout W = workspace_for(FX_R_ACCU, rows, cols, L, vec);
   if (L.split > 1 && (!ws || ws_bytes < W.total()))
     return fail(FX_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", W.total(), ws_bytes);
-  return with_vec<T>(vec, [&](auto Nc) {
+  return with_vec<T, E>(vec, [&](auto Nc) {
     return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_full<E, M, D, N, EPT>), dim3(L.split), dim3(L.block), 0, st, e, n,
@@ -497,7 +509,7 @@ int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
       return hip_check(hipGetLastError(), "k_colsum_thin launch");
     }
     const int64_t rpc = ceil_div(ceil_div(rows, L.split), vec) * vec;
-    return with_vec<T>(vec, [&](auto Nc) {
+    return with_vec<T, E>(vec, [&](auto Nc) {
       return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
         constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
         hipLaunchKernelGGL((k_colsum<E, O, N, EPT>), dim3((unsigned)cols, L.split), dim3(L.block), 0,
@@ -508,7 +520,7 @@ int reduce_dim_direct(int kind, const E& e, O* out, void* ws, size_t ws_bytes,
   }
   const int64_t cpc = ceil_div(cols, L.split);
   const int64_t rblocks = ceil_div(rows, (int64_t)L.block * vec);
-  return with_vec<T>(vec, [&](auto Nc) {
+  return with_vec<T, E>(vec, [&](auto Nc) {
     return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
       hipLaunchKernelGGL((k_rowsum<E, O, N, EPT>), dim3((unsigned)rblocks, L.split), dim3(L.block), 0,

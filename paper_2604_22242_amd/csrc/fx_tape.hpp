@@ -318,7 +318,10 @@ __device__ __forceinline__ void eval_tile(const TapeExpr<T, BYREF, SLOTS>& e, in
     for (int j = 0; j < N; ++j) r[k].v[j] = out.v[k * N + j];
 }
 
-template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static constexpr int value = 2; };
+template <class T, bool B, int S> struct max_ept<TapeExpr<T, B, S>> { static constexpr int value = 4; };
+template <class T, bool B, int S> struct vec8_compiled<TapeExpr<T, B, S>> {
+  static constexpr bool value = true;
+};
 
 // The launch configuration of an interpreted tape: the fields of cfg (NULL:
 // all) left at 0 take the interpreter's defaults for the kind and storage

@@ -64,9 +64,13 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
 
 // ---- exhaustive search -------------------------------------------------------
 //
-// The grid: block {64, 128, 256, 512} x EPT {1, 2} x vector {one element, 16
-// bytes} x four split values of the kind, in that nesting order, then the
-// library default (all fields 0).  The split values are: element-wise 0 (one
+// The grid: block {64, 128, 256, 512} x EPT {1, 2, 4} x vector {one element,
+// 8 bytes, 16 bytes} x four split values of the kind, in that nesting order,
+// then the library default (all fields 0).  Blocks stop at 512 threads: every
+// kernel is compiled for at most 512 (a 1024-thread bound would cap the
+// interpreter at 128 registers per lane, and it keeps up to 90 live in its
+// loop).  EPT 8 is not compiled for tapes (four interpreter passes of code per
+// loop, for no gain in the sweeps).  The split values are: element-wise 0 (one
 // tile per block), 2, 8 and 32 blocks per CU; accu / norm 1, 2, 4 and 8
 // blocks per CU; column sums 0 (the heuristic), 1, 4 and 16 chunks per
 // column; row sums 0 (the heuristic), 16, 64 and 256 column chunks.
@@ -74,8 +78,9 @@ extern "C" int fx_tune_time(const fx_tape* t, fx_dtype dt, const void* const* in
 namespace {
 
 constexpr int kGridBlocks[4] = {64, 128, 256, 512};
-constexpr int kGridEpts[2] = {1, 2};
-constexpr int kGridSize = 4 * 2 * 2 * 4 + 1;
+constexpr int kGridEpts[3] = {1, 2, 4};
+constexpr int kGridVecs[3] = {0, 8, 16};  // 0: one element
+constexpr int kGridSize = 4 * 3 * 3 * 4 + 1;
 
 void grid_splits(int kind, int cus, int* s) {
   switch (kind) {
@@ -112,8 +117,8 @@ extern "C" int32_t fx_tune_grid(int kind, fx_dtype dt, fx_launch* out, int32_t c
   int k = 0;
   for (int b : kGridBlocks)
     for (int e : kGridEpts)
-      for (int vb : {elem, 16})
-        for (int s : sp) out[k++] = fx_launch{b, e, vb, s};
+      for (int v : kGridVecs)
+        for (int s : sp) out[k++] = fx_launch{b, e, v ? std::max(v, elem) : elem, s};
   out[k++] = fx_launch{0, 0, 0, 0};
   return k;
 }
@@ -230,7 +235,8 @@ extern "C" int fx_autotune(const fx_tape* t, fx_dtype dt, const void* const* inp
 // Features of a tape (the model's 25 inputs, in the order the model was
 // trained on): the 8 operator counts (add, sub, schur, div, neg, abs, exp,
 // sqrt); constants, depth, instructions, slots, inputs; 1 for 2-byte
-// storage; log2 of the size, rows and columns; the result kind one-hot
+// storage; log2 of the size, rows and columns (n x 1 for element-wise
+// results and full reductions); the result kind one-hot
 // (element-wise, accu, column sums, row sums, norm); bytes per element
 // (inputs plus the output of an element-wise result); the transcendental
 // count (div + exp + sqrt); log2 of the bytes moved.
@@ -247,7 +253,11 @@ extern "C" int32_t fx_tape_features(const fx_tape* t, fx_dtype dt, fx_shape shap
   if (shape.n_rows < 0 || shape.n_cols < 0) return -fail(FX_E_ARG, "negative shape");
   if (!out || cap < kModelFeatures) return kModelFeatures;
   const fx_tape_info& I = t->info;
-  const double rows = (double)shape.n_rows, cols = (double)shape.n_cols;
+  // Element-wise results and full reductions see the data as one flat
+  // vector, so their rows / columns features are those of an n x 1 shape.
+  const bool flat = kind == 0 || kind == FX_R_ACCU || kind == FX_R_NORM;
+  const double rows = flat ? (double)shape.n_rows * (double)shape.n_cols : (double)shape.n_rows;
+  const double cols = flat ? 1.0 : (double)shape.n_cols;
   const double n = std::max(1.0, rows * cols);
   const double bpe = (double)elem * (I.n_inputs + (kind == 0 ? 1 : 0));
   int k = 0;
@@ -314,12 +324,13 @@ extern "C" int fx_model_predict(const fx_model* m, const float* features, int ki
   if (kind < 0 || kind > FX_R_NORM || kind == FX_R_DOT) return fail(FX_E_ARG, "unknown kind %d", kind);
   int32_t choice[8] = {0};
   if (int rc = fx_model_choose(m, features, choice)) return rc;
-  if (choice[0] < 0 || choice[0] > 3 || choice[1] < 0 || choice[1] > 1 || choice[2] < 0 ||
-      choice[2] > 1 || choice[3] < 0 || choice[3] > 3)
-    return fail(FX_E_ARG, "the model's heads are not block (4) / EPT (2) / vector (2) / split (4)");
+  if (choice[0] < 0 || choice[0] > 3 || choice[1] < 0 || choice[1] > 2 || choice[2] < 0 ||
+      choice[2] > 2 || choice[3] < 0 || choice[3] > 3)
+    return fail(FX_E_ARG, "the model's heads are not block (4) / EPT (3) / vector (3) / split (4)");
   int sp[4];
   grid_splits(kind, device_cus(), sp);
-  *out = fx_launch{kGridBlocks[choice[0]], kGridEpts[choice[1]], choice[2] ? 16 : elem,
+  const int v = kGridVecs[choice[2]];
+  *out = fx_launch{kGridBlocks[choice[0]], kGridEpts[choice[1]], v ? std::max(v, elem) : elem,
                    sp[choice[3]]};
   return FX_OK;
 }

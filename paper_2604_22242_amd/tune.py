@@ -25,8 +25,8 @@ from . import (BF16, F32, R_ACCU, R_COLSUM, R_NORM, R_ROWSUM, Tape, fx_tune_time
                fx_workspace_bytes, lib)
 
 BLOCKS = (64, 128, 256, 512)
-EPTS = (1, 2)
-VECS = ("elem", 16)
+EPTS = (1, 2, 4)
+VECS = ("elem", 8, 16)
 KIND = {None: 0, "accu": R_ACCU, "colsum": R_COLSUM, "rowsum": R_ROWSUM, "norm": R_NORM}
 DTYPE = {"f32": F32, "bf16": BF16}
 ELEM = {"f32": 4, "bf16": 2}
@@ -55,7 +55,7 @@ def grid(reduce, dtype, cus=256):
     for bi, b in enumerate(BLOCKS):
         for ei, e in enumerate(EPTS):
             for vi, v in enumerate(VECS):
-                vb = ELEM[dtype] if v == "elem" else v
+                vb = ELEM[dtype] if v == "elem" else max(v, ELEM[dtype])
                 for si, s in enumerate(split_choices(reduce, cus)):
                     out.append(((b, e, vb, s), (bi, ei, vi, si)))
     out.append((DEFAULT, None))
@@ -73,6 +73,9 @@ def features(info: dict, dtype: str, shape, reduce) -> list:
     """The model's input vector for one (tree, size, dtype, reduction)."""
     oc = info["op_count"]
     rows, cols = shape
+    if reduce in (None, "accu", "norm"):
+        # element-wise results and full reductions see one flat vector
+        rows, cols = rows * cols, 1
     n = max(1, rows * cols)
     bpe = ELEM[dtype] * (info["n_inputs"] + (1 if reduce is None else 0))
     red = [1.0 if reduce == r else 0.0 for r in (None, "accu", "colsum", "rowsum", "norm")]

@@ -64,7 +64,8 @@ def test_random_trees_dim_sums(dtype, e):
 
 
 @pytest.mark.parametrize("cfg", [(64, 1, 4, 0), (128, 2, 16, 0), (256, 1, 16, 5),
-                                 (512, 2, 16, 0), (256, 1, 2, 0)])
+                                 (512, 2, 16, 0), (256, 1, 2, 0), (256, 4, 16, 0),
+                                 (128, 4, 8, 0), (64, 2, 8, 7), (512, 4, 4, 0)])
 def test_tape_configs(cfg):
     torch, fx = need_gpu()
     nodes, k, _ = trees.random_tree(5, 11, depth=(6, 8))
@@ -77,13 +78,18 @@ def test_tape_configs(cfg):
             continue
         _run(fx, torch, nodes, k, 5, 11, dtype, (3 * 4096 + 5, 1), 0, cfg)
         _run(fx, torch, nodes, k, 5, 11, dtype, (3 * 4096 + 5, 1), fx.R_ACCU, cfg)
+        if cfg[2] in (8, 16) and cfg[1] == 4:   # the widths only tapes are compiled for
+            _run(fx, torch, nodes, k, 5, 11, dtype, (1024, 77), fx.R_COLSUM, cfg[:3] + (0,))
+            _run(fx, torch, nodes, k, 5, 11, dtype, (1000, 64), fx.R_ROWSUM, cfg[:3] + (0,))
+            _run(fx, torch, nodes, k, 5, 11, dtype, (4096, 20), fx.R_NORM, cfg)
 
 
 def test_tape_ept_cap():
+    # tapes are compiled for EPT 1, 2 and 4; an explicit EPT 8 is refused
     torch, fx = need_gpu()
     nodes, k, _ = trees.random_tree(4, 3)
     with pytest.raises(fx.FxError) as ei:
-        _run(fx, torch, nodes, k, 4, 3, "f32", (4096, 1), 0, (256, 4, 16, 0))
+        _run(fx, torch, nodes, k, 4, 3, "f32", (4096, 1), 0, (256, 8, 16, 0))
     assert ei.value.code == 6
 
 

@@ -48,6 +48,20 @@ def test_choice_for_the_matrix_workload():
     import paper_2604_22242_amd as fx
     info = fx.Tape(model.C2_NODES).info()
     ch = choose(tune.features(info, "f32", (8192, 8192), None))
-    # the evaluation report's pick for the fused Z: 128 threads, EPT 1, 16 B,
-    # 32 blocks per CU
-    assert model.config_of(ch, None, "f32") == (128, 1, 16, 32 * 256)
+    # the evaluation report's pick for the fused Z: 64 threads, EPT 1, 16 B,
+    # one tile per block
+    assert model.config_of(ch, None, "f32") == (64, 1, 16, 0)
+
+
+def test_unused_features_carry_no_weight():
+    # the training trees never hold a neg node (exp(-|a|) is built as
+    # 0 - |a|), so that count is 0 on every training row: its first-layer
+    # weights start at zero and get no gradient, and a tree that does hold
+    # one (the matrix workload's exp(-|W|)) is scored as if it had none
+    meta, W1, *_ = _load()
+    neg = meta["features"].index("neg")
+    assert meta["std"][neg] == 1.0 and meta["mean"][neg] == 0.0
+    assert not W1[:, neg].any()
+    p = model.init_params(5, 4, 3, seed=1, constant=[2])
+    W = p[:20].reshape(4, 5)
+    assert not W[:, 2].any() and W[:, [0, 1, 3, 4]].all()

@@ -11,12 +11,13 @@ def test_grid_shape_and_labels():
     for red in (None, "accu", "colsum", "rowsum", "norm"):
         for dt in ("f32", "bf16"):
             g = tune.grid(red, dt)
-            assert len(g) == 4 * 2 * 2 * 4 + 1 and g[-1] == (tune.DEFAULT, None)
+            assert len(g) == 4 * 3 * 3 * 4 + 1 and g[-1] == (tune.DEFAULT, None)
             g = g[:-1]
             assert len({c for c, _ in g}) == len(g)
             for (b, e, v, s), (bi, ei, vi, si) in g:
                 assert tune.BLOCKS[bi] == b and tune.EPTS[ei] == e
-                assert v == (tune.ELEM[dt] if tune.VECS[vi] == "elem" else 16)
+                assert v == (tune.ELEM[dt] if tune.VECS[vi] == "elem"
+                             else max(tune.VECS[vi], tune.ELEM[dt]))
                 assert tune.split_choices(red)[si] == s
 
 
@@ -94,6 +95,16 @@ def test_native_features_match_the_driver():
         got = fx.fx_tape_features(tape, codes[item["dtype"]], item["shape"], kinds[item["reduce"]])
         want = tune.features(tape.info(), item["dtype"], item["shape"], item["reduce"])
         assert np.array_equal(np.float32(got), np.float32(want)), (i, got, want)
+    # element-wise results and full reductions are flat: a matrix shape gives
+    # the features of its n x 1 vector (the shape every tuning item of those
+    # kinds has), in C and in the driver alike; dimension sums keep the shape
+    tape = fx.Tape(trees.tuning_item(5, 0)["nodes"])
+    for red in (None, "accu", "colsum", "rowsum", "norm"):
+        got = fx.fx_tape_features(tape, fx.F32, (8192, 4096), kinds[red])
+        flat = fx.fx_tape_features(tape, fx.F32, (8192 * 4096, 1), kinds[red])
+        want = tune.features(tape.info(), "f32", (8192, 4096), red)
+        assert np.array_equal(np.float32(got), np.float32(want)), red
+        assert np.array_equal(np.float32(got), np.float32(flat)) == (red not in ("colsum", "rowsum"))
 
 
 def test_model_file_layout(tmp_path):
@@ -126,7 +137,7 @@ def test_count_returning_calls_report_errors_as_negative_status():
     L = fx.lib()
     assert L.fx_tune_grid(0, fx.U32, None, 0) == -3        # FX_E_DTYPE
     assert L.fx_tune_grid(99, fx.F32, None, 0) == -1       # FX_E_ARG
-    assert L.fx_tune_grid(0, fx.F32, None, 0) == 65
+    assert L.fx_tune_grid(0, fx.F32, None, 0) == 145
     tape = fx.Tape([("leaf", -1, -1, 0, 0.0), ("exp", 0, -1, -1, 0.0)])
     shape = fx.Shape(100, 1)
     assert L.fx_tape_features(tape.handle, fx.U32, shape, 0, None, 0) == -3
