@@ -25,7 +25,9 @@
 #include "fx_expr.hpp"
 
 // Cache policy of streamed loads and stores (measured on MI355X: streaming
-// loads raise the read ceiling from 6.4 to 7.1 TB/s; stores are neutral).
+// loads raise the read ceiling from 6.4 to 7.1 TB/s).  FX_NT_STORES forces
+// streaming stores everywhere; by default the element-wise kernel chooses
+// per launch from the size of its output (kStreamStoresAbove).
 #ifndef FX_NT_LOADS
 #define FX_NT_LOADS 1
 #endif
@@ -39,6 +41,13 @@ namespace fx {
 constexpr int kMaxBlock = 512;
 constexpr bool kNT = FX_NT_LOADS != 0;    // streaming policy for loads
 constexpr bool kNTS = FX_NT_STORES != 0;  // streaming policy for stores
+
+// Outputs larger than MI355X's 256 MiB last-level cache (the Infinity Cache)
+// are written with streaming stores.  Measured for X%Y + 2W in FP32: up to a
+// 256 MiB output, ordinary stores run at 6.6-6.7 TB/s (the output stays in
+// that cache) against 6.1-6.2 streaming; from 320 MiB on, ordinary stores
+// fall to 6.0-6.1 TB/s and streaming stores keep 6.2-6.3.
+constexpr uint64_t kStreamStoresAbove = uint64_t(256) << 20;
 
 // Maps applied to each element before summation.
 struct map_id {
@@ -109,7 +118,10 @@ __device__ __forceinline__ void eval_tile(const Fused<E>& f, int64_t base, int64
 // ============================================================================
 // Element-wise: Z[i] = E(i), i < n.
 
-template <class E, class T, int N, int EPT>
+// NTS: streaming stores.  The policy is a template parameter: a run-time
+// choice between two otherwise identical stores is merged by the compiler
+// into one store, which drops the streaming hint.
+template <class E, class T, int N, int EPT, bool NTS>
 __global__ __launch_bounds__(kMaxBlock) void k_ew(E e, T* __restrict__ z, int64_t n) {
   using C = typename E::ct;
   const int64_t nv = n / N;  // whole vectors
@@ -122,12 +134,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_ew(E e, T* __restrict__ z, int64_
       lanes<C, N> r[EPT];
       eval_tile<N, EPT>(e, v0 * N, (int64_t)blockDim.x * N, r);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) store_lanes<N, kNTS>(z, (v0 + k * blockDim.x) * N, r[k]);
+      for (int k = 0; k < EPT; ++k) store_lanes<N, NTS>(z, (v0 + k * blockDim.x) * N, r[k]);
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int64_t v = v0 + k * blockDim.x;
-        if (v < nv) store_lanes<N, kNTS>(z, v * N, e.template at_vec<N, kNT>(v * N));
+        if (v < nv) store_lanes<N, NTS>(z, v * N, e.template at_vec<N, kNT>(v * N));
       }
     }
   }
@@ -411,7 +423,15 @@ int eval_direct(T* z, const E& e, const fx_launch* cfg, hipStream_t st) {
   return with_vec<T, E>(vec, [&](auto Nc) {
     return with_ept<max_ept<E>::value>(L.ept, [&](auto Ec) {
       constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
-      hipLaunchKernelGGL((k_ew<E, T, N, EPT>), dim3(L.split), dim3(L.block), 0, st, e, z, n);
+      // (streaming stores are compiled for 16-byte vectors, the default for
+      // outputs of that size)
+      if constexpr (N * sizeof(T) == 16) {
+        if (kNTS || (uint64_t)n * sizeof(T) > kStreamStoresAbove) {
+          hipLaunchKernelGGL((k_ew<E, T, N, EPT, true>), dim3(L.split), dim3(L.block), 0, st, e, z, n);
+          return hip_check(hipGetLastError(), "k_ew launch");
+        }
+      }
+      hipLaunchKernelGGL((k_ew<E, T, N, EPT, kNTS>), dim3(L.split), dim3(L.block), 0, st, e, z, n);
       return hip_check(hipGetLastError(), "k_ew launch");
     });
   });

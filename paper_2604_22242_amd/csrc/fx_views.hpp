@@ -377,7 +377,7 @@ __device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t G) {
 template <int KT> constexpr int kRowVecs = KT > 0 ? 16 : 64;        // thread rows per tile
 template <int KT> constexpr int kColsPerTile = KT > 0 ? kTileCols : 16;
 
-template <class E, class T, int N>
+template <class E, class T, int N, bool NTS>
 __global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, int64_t rows,
                                                       int64_t cols, uint32_t tile_rows) {
   using C = typename E::ct;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kTileThreads) void k_ew2d(E e, T* __restrict__ z, i
     const int64_t c = x.c0 + cg + CG * q;
     if (c >= cols || r >= rows) continue;
     if (r + N <= rows) {
-      store_lanes<N, kNTS>(z, r + c * rows, at2<0, N>(e, r, c, x));
+      store_lanes<N, NTS>(z, r + c * rows, at2<0, N>(e, r, c, x));
     } else {
       for (int j = 0; r + j < rows; ++j) z[r + j + c * rows] = static_cast<T>(at2<0, 1>(e, r + j, c, x).v[0]);
     }
@@ -498,7 +498,7 @@ __device__ __forceinline__ lanes<float, 4> at2p(const Binary<Op, A, B>& e, int64
 
 // One block per tile pair I <= J (p enumerates them column by column); n x n
 // FP32 result, n a multiple of 4.
-template <class E>
+template <class E, bool NTS>
 __global__ __launch_bounds__(kTileThreads) void k_ew2d_pair(E e, pair_tab tab, float* __restrict__ z,
                                                            int64_t n) {
   __shared__ float lds[2 * kPairMats * kPairBuf];
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(kTileThreads) void k_ew2d_pair(E e, pair_tab tab, f
 #pragma unroll
     for (int q = 0; q < kPairT / 16; ++q) {
       const int64_t c = x.c0 + cg + 16 * q;
-      if (c < n && r < n) store_lanes<4, kNTS>(z, r + c * n, at2p<0>(e, r, c, x));
+      if (c < n && r < n) store_lanes<4, NTS>(z, r + c * n, at2p<0>(e, r, c, x));
     }
   }
 }
@@ -636,13 +636,18 @@ int eval_views(T* z, const E& e, hipStream_t st) {
   const bool vec = vec_ok(e, NV) && rows % NV == 0 &&
                    reinterpret_cast<uintptr_t>(z) % 16 == 0;
   constexpr int KT = trans_count<E>::value;
+  const bool nts = kNTS || (uint64_t)rows * (uint64_t)cols * sizeof(T) > kStreamStoresAbove;
   if constexpr (KT > 0 && pairable<E>::value && std::is_same_v<T, float> &&
                 std::is_same_v<typename E::ct, float>) {
     pair_tab tab;
     if (rows == cols && pair_plan(e, rows, z, &tab)) {
       const int64_t t = ceil_div(rows, (int64_t)kPairT);
-      hipLaunchKernelGGL((k_ew2d_pair<E>), dim3((unsigned)(t * (t + 1) / 2)), dim3(kTileThreads), 0,
-                         st, e, tab, z, rows);
+      if (nts)
+        hipLaunchKernelGGL((k_ew2d_pair<E, true>), dim3((unsigned)(t * (t + 1) / 2)),
+                           dim3(kTileThreads), 0, st, e, tab, z, rows);
+      else
+        hipLaunchKernelGGL((k_ew2d_pair<E, false>), dim3((unsigned)(t * (t + 1) / 2)),
+                           dim3(kTileThreads), 0, st, e, tab, z, rows);
       return hip_check(hipGetLastError(), "k_ew2d_pair launch");
     }
   }
@@ -650,13 +655,13 @@ int eval_views(T* z, const E& e, hipStream_t st) {
   const int64_t tr = ceil_div(rows, (int64_t)kRowVecs<KT> * (vec ? NV : 1));
   if (tr * tc > 0x7fffffff)
     return fail(FX_E_UNSUPPORTED, "%lld x %lld exceeds the tile grid", (long long)rows, (long long)cols);
-  if (vec) {
-    hipLaunchKernelGGL((k_ew2d<E, T, NV>), dim3((unsigned)(tr * tc)), dim3(kTileThreads), 0, st, e,
-                       z, rows, cols, (uint32_t)tr);
-  } else {
-    hipLaunchKernelGGL((k_ew2d<E, T, 1>), dim3((unsigned)(tr * tc)), dim3(kTileThreads), 0, st, e,
-                       z, rows, cols, (uint32_t)tr);
-  }
+  const dim3 grid((unsigned)(tr * tc)), block(kTileThreads);
+  if (vec && nts)
+    hipLaunchKernelGGL((k_ew2d<E, T, NV, true>), grid, block, 0, st, e, z, rows, cols, (uint32_t)tr);
+  else if (vec)
+    hipLaunchKernelGGL((k_ew2d<E, T, NV, false>), grid, block, 0, st, e, z, rows, cols, (uint32_t)tr);
+  else
+    hipLaunchKernelGGL((k_ew2d<E, T, 1, false>), grid, block, 0, st, e, z, rows, cols, (uint32_t)tr);
   return hip_check(hipGetLastError(), "k_ew2d launch");
 }
 
