@@ -58,7 +58,7 @@ __device__ __forceinline__ lanes<ct_t<T>, N> gload_lanes(const T* p, int64_t i) 
 template <class T> __device__ __forceinline__ ct_t<T> gload(const T* p, int64_t i) {
   return static_cast<ct_t<T>>(*(const FX_GLOBAL T*)(p + i));
 }
-template <int N, class T>
+template <int N, bool NTS, class T>
 __device__ __forceinline__ void gstore_lanes(T* p, int64_t i, const lanes<ct_t<T>, N>& x) {
   using R = typename raw<N * (int)sizeof(T)>::type;
   T s[N];
@@ -67,7 +67,7 @@ __device__ __forceinline__ void gstore_lanes(T* p, int64_t i, const lanes<ct_t<T
   R r;
   __builtin_memcpy(&r, s, sizeof(R));
   FX_GLOBAL R* q = (FX_GLOBAL R*)(p + i);
-  if (kNTS) __builtin_nontemporal_store(r, q);
+  if (NTS) __builtin_nontemporal_store(r, q);
   else *q = r;
 }
 template <class T> __device__ __forceinline__ void gstore(T* p, int64_t i, ct_t<T> v) {
@@ -100,7 +100,9 @@ __device__ __forceinline__ void batch_load_tail(const X& x, int n_in, int64_t ba
   }
 }
 
-template <class T, int N, int EPT, int SLOTS>
+// NTS: streaming stores for the element-wise outputs (chosen by the host when
+// they add up to more than the last-level cache, as for single launches).
+template <class T, int N, int EPT, int SLOTS, bool NTS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restrict__ descs,
                                                    const tape_prog* __restrict__ progs,
                                                    const batch_tile* __restrict__ tiles,
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(const batch_desc* __restric
 #pragma unroll
           for (int j = 0; j < N; ++j) v.v[j] = r.v[k * N + j];
           if (ew) {
-            gstore_lanes<N>(z, base + k * stride, v);
+            gstore_lanes<N, NTS>(z, base + k * stride, v);
           } else {
 #pragma unroll
             for (int j = 0; j < N; ++j) acc.add(v.v[j]);
@@ -237,6 +239,7 @@ struct fx_batch {
   hipStream_t last_stream = nullptr;
   int vec;
   bool small_slots;  // every program fits the 8-slot file
+  bool nts;          // streaming stores (element-wise outputs beyond the last-level cache)
 };
 
 // Release paths cannot report errors: a failure here only means the context
@@ -283,9 +286,9 @@ static int batch_resident_blocks(fx_dtype dt, int vec, int ept, bool small_slots
     int nb = 0;
     const hipError_t e =
         small_slots ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                          &nb, k_batch<T, N, EPT, kTapeSmallSlots>, block, 0)
+                          &nb, k_batch<T, N, EPT, kTapeSmallSlots, false>, block, 0)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                          &nb, k_batch<T, N, EPT, kTapeMaxSlots>, block, 0);
+                          &nb, k_batch<T, N, EPT, kTapeMaxSlots, false>, block, 0);
     if (int rc = hip_check(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor")) return rc;
     *out = nb > 0 ? nb : 1;
     return (int)FX_OK;
@@ -298,15 +301,20 @@ static int batch_run(fx_batch* b, hipStream_t st) {
   return batch_dispatch(b->dt, b->vec, I.ept, [&](auto tg, auto Nc, auto Ec) {
     using T = typename decltype(tg)::type;
     constexpr int N = decltype(Nc)::value, EPT = decltype(Ec)::value;
-    if (b->small_slots)
-      hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeSmallSlots>), dim3(I.grid), dim3(I.block), 0, st,
-                         b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
-                         b->d_partials, b->d_counters, b->d_queue);
-    else
-      hipLaunchKernelGGL((k_batch<T, N, EPT, kTapeMaxSlots>), dim3(I.grid), dim3(I.block), 0, st,
-                         b->d_descs, b->d_progs, b->d_tiles, I.n_tiles, I.tile_elems,
-                         b->d_partials, b->d_counters, b->d_queue);
-    return hip_check(hipGetLastError(), "k_batch launch");
+    auto go = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, dim3(I.grid), dim3(I.block), 0, st, b->d_descs, b->d_progs,
+                         b->d_tiles, I.n_tiles, I.tile_elems, b->d_partials, b->d_counters,
+                         b->d_queue);
+      return hip_check(hipGetLastError(), "k_batch launch");
+    };
+    // streaming stores are compiled for 16-byte vectors only
+    if constexpr (N * sizeof(T) == 16) {
+      if (b->nts)
+        return b->small_slots ? go(k_batch<T, N, EPT, kTapeSmallSlots, true>)
+                              : go(k_batch<T, N, EPT, kTapeMaxSlots, true>);
+    }
+    return b->small_slots ? go(k_batch<T, N, EPT, kTapeSmallSlots, kNTS>)
+                          : go(k_batch<T, N, EPT, kTapeMaxSlots, kNTS>);
   });
 }
 
@@ -393,6 +401,12 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     I.bytes += (int64_t)elem * it.n * (it.tape->prog.n_in + (it.kind == 0 ? 1 : 0));
   }
   I.n_tiles = first;
+  {
+    uint64_t ew_bytes = 0;
+    for (int i = 0; i < count; ++i)
+      if (items[i].kind == 0) ew_bytes += (uint64_t)elem * (uint64_t)items[i].n;
+    b->nts = kNTS || ew_bytes > kStreamStoresAbove;
+  }
   {  // the queue hands out the costliest tiles first (ties: table order)
     std::vector<int64_t> order(tiles.size());
     std::iota(order.begin(), order.end(), 0);
