@@ -58,6 +58,26 @@ def test_c1_z_configs(dtype, cfg):
     assert_close(from_dev(Z, dtype), v, mu, dtype, "c1_z cfg %s" % (cfg,), out_dtype=out)
 
 
+# Outputs just below and just above the 256 MiB last-level cache: the first
+# take ordinary stores, the second streaming stores; every element, ragged
+# tails included, must match the oracle either way.
+@pytest.mark.parametrize("dtype,n", [("f32", (1 << 26) - 59), ("f32", (1 << 26) + 37),
+                                     ("bf16", (1 << 27) + 37), ("u32", (1 << 26) + 37)])
+def test_store_policy_both_sides(dtype, n):
+    torch, fx = need_gpu()
+    host, (X, Y, W) = inputs(1, n, dtype)
+    Z = empty(n, dtype)
+    fx.fx_c1_z(X, Y, W, Z)
+    torch.cuda.synchronize()
+    if dtype == "u32":
+        want, _ = oracle.evaluate_u32(oracle.EXPRS["u32_z"], host)
+        assert np.array_equal(from_dev(Z, "u32"), want)
+        return
+    v, mu = oracle.evaluate(oracle.EXPRS["c1_z"], host, dtype)
+    out = dtype if dtype in ("bf16", "f16") else None
+    assert_close(from_dev(Z, dtype), v, mu, dtype, "c1_z %s n=%d" % (dtype, n), out_dtype=out)
+
+
 @pytest.mark.parametrize("n", NS)
 def test_c1_z_u32_bit_exact(n):
     torch, fx = need_gpu()
