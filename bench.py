@@ -214,12 +214,19 @@ def ceilings_detail(fx, torch, stream, reps=5):
     return out
 
 
-def event_ms(torch, stream, fn, reps):
-    """Mean HIP-event time of fn() over reps launches after two warm-ups."""
+def event_ms(torch, stream, fn, reps, warm_ms=5.0):
+    """Mean HIP-event time of fn() over reps launches after a warm-up of at
+    least two launches and about warm_ms of GPU time."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
     for _ in range(2):
         fn()
+    b.record(stream)
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    each = max(a.elapsed_time(b) / 2, 1e-3)
+    for _ in range(min(200, int(warm_ms / each))):
+        fn()
+    torch.cuda.synchronize()
     a.record(stream)
     for _ in range(reps):
         fn()
@@ -322,8 +329,13 @@ def batch_detail(fx, torch, stream, reps):
     info = b.info()
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        g = event_ms(torch, st, lambda: b.graph(st), reps)
-        one = event_ms(torch, st, lambda: b.launch(st), reps)
+        # medians over three interleaved rounds: the first round after the
+        # batch is built runs several percent slow
+        gs, ones = [], []
+        for _ in range(3):
+            gs.append(event_ms(torch, st, lambda: b.graph(st), reps))
+            ones.append(event_ms(torch, st, lambda: b.launch(st), reps))
+        g, one = statistics.median(gs), statistics.median(ones)
         each = event_ms(torch, st, lambda: b.launch_each(st), max(3, reps // 5))
     res = {"expressions": 4096, "tiles": info["n_tiles"], "tile_elems": info["tile_elems"],
            "bytes": info["bytes"], "graph_ms": round(g, 4), "persistent_launch_ms": round(one, 4),
