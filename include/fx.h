@@ -486,12 +486,13 @@ typedef struct {
 typedef struct fx_batch fx_batch;
 
 /* Build a batch (synchronous: allocates and uploads its device tables, owned
- * by the batch).  cfg: block / ept / vec_bytes as elsewhere (0 = 256 threads,
- * 16-byte vectors, and as many vectors per thread as fill one interpreter
- * pass: 2 for FP32 and FP64 storage, 1 for half storage), split = grid of
- * the persistent kernel (0 = as many blocks as the device holds at once);
- * tile_elems: elements per tile (0 = 32768; rounded up to whole block
- * passes).  Tiles are handed out from a work queue, costliest first.  Item
+ * by the batch).  cfg: block / ept / vec_bytes as elsewhere (0 = 512 threads
+ * for 4- and 8-byte storage, 256 for half storage; 16-byte vectors; and as
+ * many vectors per thread as fill one interpreter pass: 2 for FP32 and FP64
+ * storage, 1 for half storage), split = grid of the persistent kernel (0 =
+ * as many blocks as the device holds at once); tile_elems: elements per tile
+ * (0 = 16 block passes: 65536 for FP32, 32768 for FP64 and half storage with
+ * the default block; rounded up to whole block passes).  Tiles are handed out from a work queue, costliest first.  Item
  * pointers must stay valid while the batch is used. */
 int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt,
                     const fx_launch* cfg, int64_t tile_elems, fx_batch** out);

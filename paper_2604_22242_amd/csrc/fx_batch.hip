@@ -353,7 +353,10 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
   fx_batch_info& I = b->info;
   I = fx_batch_info{};
   I.count = count;
-  I.block = c.block ? c.block : 256;
+  // 512 threads for 4- and 8-byte storage, 256 for half storage (4096-tree
+  // batch, graph replays: FP32 0.355 against 0.367 ms with 256; half storage
+  // 0.322 with 256 against 0.355 with 512)
+  I.block = c.block ? c.block : (elem >= 4 ? 512 : 256);
   I.vec_bytes = (c.vec_bytes ? std::max(c.vec_bytes, elem) : 16);
   if (addr_or & 15) I.vec_bytes = elem;  // every pointer must be 16-byte aligned for vectors
   b->vec = I.vec_bytes / elem;
@@ -365,7 +368,8 @@ int fx_batch_create(const fx_batch_item* items, int32_t count, fx_dtype dt, cons
     I.ept = c.ept ? c.ept : std::max(1, std::min(2, pass_lanes / b->vec));
   }
   const int64_t pass = (int64_t)I.block * I.ept * b->vec;
-  const int64_t want = tile_elems ? tile_elems : 32768;
+  // default tile: 16 block passes (65536 FP32 elements, 32768 FP64 or half)
+  const int64_t want = tile_elems ? tile_elems : 16 * pass;
   I.tile_elems = ceil_div(want, pass) * pass;
   // tile table
   std::vector<batch_desc> descs(count);
