@@ -129,6 +129,14 @@ def time_steps(torch, run, steps, warmup, stream, timed=RESULTS):
     return wall, ms
 
 
+def spin_up(run, steps=20):
+    """Untimed steps before a detail pass: the first milliseconds after a
+    workload's inputs are built run several percent slow."""
+    for _ in range(steps):
+        for r in RESULTS:
+            run(r, None)
+
+
 def copy_ceiling(fx, torch, stream, nbytes=1 << 31, reps=20):
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -214,9 +222,31 @@ def ceilings_detail(fx, torch, stream, reps=5):
     return out
 
 
+_SLEEP_CYCLES_PER_MS = None
+
+
+def hold_stream(torch, stream, ms):
+    """Keep `stream` busy for about `ms` with a GPU-side spin that touches no
+    memory, so that work enqueued meanwhile starts back to back."""
+    global _SLEEP_CYCLES_PER_MS
+    if not hasattr(torch.cuda, "_sleep"):
+        return
+    with torch.cuda.stream(stream):
+        if _SLEEP_CYCLES_PER_MS is None:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            torch.cuda._sleep(1_000_000)
+            b.record(stream)
+            torch.cuda.synchronize()
+            _SLEEP_CYCLES_PER_MS = 1_000_000 / max(a.elapsed_time(b), 1e-3)
+        torch.cuda._sleep(int(_SLEEP_CYCLES_PER_MS * ms))
+
+
 def event_ms(torch, stream, fn, reps, warm_ms=5.0):
     """Mean HIP-event time of fn() over reps launches after a warm-up of at
-    least two launches and about warm_ms of GPU time."""
+    least two launches and about warm_ms of GPU time.  Short kernels are
+    enqueued behind a GPU-side spin, so that they are timed back to back on
+    the GPU rather than at the host's launch rate."""
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(2):
@@ -227,6 +257,8 @@ def event_ms(torch, stream, fn, reps, warm_ms=5.0):
     for _ in range(min(200, int(warm_ms / each))):
         fn()
     torch.cuda.synchronize()
+    if each < 0.1:
+        hold_stream(torch, stream, min(10.0, 0.05 * reps))
     a.record(stream)
     for _ in range(reps):
         fn()
@@ -694,12 +726,10 @@ def main():
         return
     log("bench: fused FP32 %dx%d, %d warm-up + %d timed steps" % (ROWS, COLS, a.warmup, a.steps))
     wl = Workload(fx, torch, "f32", ROWS, COLS)
-    # per-result kernel times (their own pass, after 20 untimed steps: the
-    # first milliseconds after the inputs are built run several percent
-    # slow), then the timed steps with events around the dominant kernel only
-    for _ in range(0 if a.profile else 20):
-        for r in RESULTS:
-            wl.fused(r, stream)
+    # per-result kernel times (their own pass, after untimed steps), then
+    # the timed steps with events around the dominant kernel only
+    if not a.profile:
+        spin_up(lambda r, _: wl.fused(r, stream))
     _, ms = time_steps(torch, wl.fused, a.steps, a.warmup, stream)
     dominant = max(RESULTS, key=lambda r: ms[r])
     wall, dms_live = time_steps(torch, wl.fused, a.steps, a.warmup, stream, timed=(dominant,))
@@ -728,6 +758,7 @@ def main():
 
     if not a.no_extra:
         log("bench: unfused FP32 baseline")
+        spin_up(lambda r, _: wl.unfused(r, stream))
         _, ums = time_steps(torch, wl.unfused, a.steps, a.warmup, stream)
         detail["fp32_unfused_ms"] = {r: round(ums[r], 5) for r in RESULTS}
         detail["speedup_vs_unfused"] = {r: round(ums[r] / ms[r], 3) for r in RESULTS}
@@ -735,7 +766,9 @@ def main():
         torch.cuda.empty_cache()
         log("bench: fused BF16 storage")
         wb = Workload(fx, torch, "bf16", ROWS, COLS)
+        spin_up(lambda r, _: wb.fused(r, stream))
         _, bms = time_steps(torch, wb.fused, a.steps, a.warmup, stream)
+        spin_up(lambda r, _: wb.unfused(r, stream))
         _, bums = time_steps(torch, wb.unfused, a.steps, a.warmup, stream)
         detail["bf16_fused"] = {r: {"ms": round(bms[r], 5),
                                     "GB/s": round(wb.bytes[r] / (bms[r] * 1e-3) / 1e9, 1),
@@ -752,7 +785,9 @@ def main():
         torch.cuda.empty_cache()
         log("bench: fused FP64 storage")
         wd = Workload(fx, torch, "f64", ROWS, COLS)
+        spin_up(lambda r, _: wd.fused(r, stream))
         _, dms = time_steps(torch, wd.fused, a.steps, a.warmup, stream)
+        spin_up(lambda r, _: wd.unfused(r, stream))
         _, dums = time_steps(torch, wd.unfused, a.steps, a.warmup, stream)
         detail["fp64_fused"] = {r: {"ms": round(dms[r], 5),
                                     "GB/s": round(wd.bytes[r] / (dms[r] * 1e-3) / 1e9, 1)}
