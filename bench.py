@@ -244,10 +244,12 @@ def hold_stream(torch, stream, ms):
 
 def event_ms(torch, stream, fn, reps, warm_ms=5.0):
     """Mean HIP-event time of fn() over reps launches after a warm-up of at
-    least two launches and about warm_ms of GPU time.  Short kernels are
+    least three launches and about warm_ms of GPU time.  Short kernels are
     enqueued behind a GPU-side spin, so that they are timed back to back on
     the GPU rather than at the host's launch rate."""
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()  # a first launch may load the kernel's code
+    torch.cuda.synchronize()
     a.record(stream)
     for _ in range(2):
         fn()
