@@ -35,6 +35,10 @@
  *     element-wise loads otherwise.
  *   - An element-wise output may be exactly one of the inputs (in place);
  *     partial overlap is not allowed.
+ *   - Inputs are read with streaming (nontemporal) loads.  An element-wise
+ *     output larger than 256 MiB (MI355X's last-level cache) that is written
+ *     with 16-byte vectors is written with streaming stores, so it is not
+ *     left in that cache; smaller outputs use ordinary stores.
  *
  * Workspaces: reductions that combine results across blocks take a caller
  * allocated device workspace of fx_workspace_bytes() bytes, which must be
